@@ -1,0 +1,283 @@
+"""Seeded synthetic inputs for galaxy-profile fitting.
+
+This module draws what a survey would hand to the fitter -- cutout sizes,
+true profile parameters, PSF kernels, sky levels, noise -- and turns a
+noiseless *unit-flux* model image into data and sigma images.  It holds none
+of the fitting method's arithmetic: the galaxy model image itself is rendered
+by whichever side needs it (the HIP library for the benchmark, the FP64
+oracle for parity tests), and only its linear scaling to the drawn
+signal-to-noise, sky and noise happens here.
+
+Random streams: galaxy ``i`` of configuration ``cfg`` with seed ``seed`` draws
+its parameters from ``PCG64(SeedSequence([seed, cfg, i, 0]))`` and its noise
+from ``PCG64(SeedSequence([seed, cfg, i, 1]))``, so any subset regenerates
+independently of batching.
+
+Workloads (the distributions the fitter is benchmarked on):
+  * ``sersic64``  -- 64x64 cutouts, single Sersic + flat sky, Gaussian PSF of
+    FWHM 1.5 px on 15x15 (pixel-integrated), sigma = 1, Gaussian noise;
+  * ``uneven``    -- square cutouts log-uniform in [48, 256] px, a circular
+    Moffat PSF per galaxy (beta 2.5-4.5, FWHM 1.2-2.5 px, 25x25), Poisson
+    plus 5 e- read noise;
+  * ``bulgedisk`` -- 128x128, Sersic bulge + exponential disk with a shared
+    centre, PSF and noise as ``uneven``.
+Common Sersic draw: centre (W/2, H/2) + U(-2, 2) px, r_e log-uniform
+[2, 15] px, n U(0.5, 6), q U(0.3, 1), PA U(0, 180) deg, peak SNR
+log-uniform [20, 200] (peak of the noiseless convolved galaxy without sky
+over the noise sigma at that pixel).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from scipy.special import erf
+
+M0 = 22.5
+READ_NOISE = 5.0
+
+# profile type codes shared by the C interfaces of both implementations
+SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
+
+# Model layouts: list of (type, convolve, idx per natural slot, fixed values).
+# Parameter vector of "sersic": x0 y0 mag re n q pa sky.
+# Parameter vector of "bulgedisk": x0 y0 | mag_b re_b n_b q_b pa_b | mag_d rs_d q_d pa_d | sky.
+MODEL_SPECS: Dict[str, dict] = {
+    "sersic": dict(
+        p=8,
+        comps=[
+            (SERSIC, 1, [0, 1, 2, 3, 4, 5, 6], []),
+            (SKY, 0, [7], []),
+        ],
+        names=["x0", "y0", "mag", "re", "n", "q", "pa", "sky"],
+    ),
+    "bulgedisk": dict(
+        p=12,
+        comps=[
+            (SERSIC, 1, [0, 1, 2, 3, 4, 5, 6], []),
+            (EXPDISK, 1, [0, 1, 7, 8, 9, 10], []),
+            (SKY, 0, [11], []),
+        ],
+        names=["x0", "y0", "mag_b", "re_b", "n_b", "q_b", "pa_b", "mag_d", "rs_d", "q_d", "pa_d", "sky"],
+    ),
+}
+
+CONFIG_IDS = {"sersic64": 1, "uneven": 2, "bulgedisk": 3}
+
+
+def _rng(seed: int, cfg: int, i: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, cfg, i, stream])))
+
+
+def gaussian_psf(fwhm: float, k: int) -> np.ndarray:
+    """Circular Gaussian kernel integrated over each pixel (erf), sum 1."""
+    s = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    c = (k - 1) / 2.0
+    e = np.arange(k + 1, dtype=np.float64) - c - 0.5
+    cdf = 0.5 * (1.0 + erf(e / (math.sqrt(2.0) * s)))
+    p1 = np.diff(cdf)
+    ker = np.outer(p1, p1)
+    return (ker / ker.sum()).astype(np.float32)
+
+
+def moffat_psf(beta: float, fwhm: float, k: int, sub: int = 10) -> np.ndarray:
+    """Circular Moffat kernel, each pixel the mean of sub x sub samples, sum 1."""
+    rd = fwhm / (2.0 * math.sqrt(2.0 ** (1.0 / beta) - 1.0))
+    c = (k - 1) / 2.0
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    ax = (np.arange(k)[:, None] - c + off[None, :]).reshape(-1)
+    r2 = ax[:, None] ** 2 + ax[None, :] ** 2
+    v = (1.0 + r2 / (rd * rd)) ** (-beta)
+    ker = v.reshape(k, sub, k, sub).mean(axis=(1, 3))
+    return (ker / ker.sum()).astype(np.float32)
+
+
+@dataclass
+class Batch:
+    """A ragged batch: concatenated row-major cutouts and PSFs."""
+
+    config: str
+    model: str
+    h: np.ndarray            # int32 [n]
+    w: np.ndarray            # int32 [n]
+    img_off: np.ndarray      # int64 [n] offsets into the pixel arrays
+    psf_k: np.ndarray        # int32 [n]
+    psf_off: np.ndarray      # int64 [n]
+    psf: np.ndarray          # float32, concatenated K*K kernels
+    truth: np.ndarray        # float64 [n, p]; magnitudes filled by finish()
+    snr: np.ndarray          # float64 [n]
+    sky: np.ndarray          # float64 [n]
+    index: np.ndarray        # int64 [n] galaxy indices within the configuration
+    seed: int = 0
+    data: Optional[np.ndarray] = None    # float32, filled by finish()
+    sigma: Optional[np.ndarray] = None
+
+    @property
+    def n(self) -> int:
+        return len(self.h)
+
+    @property
+    def npix(self) -> int:
+        return int(self.img_off[-1] + self.h[-1].astype(np.int64) * self.w[-1]) if self.n else 0
+
+    def image(self, arr: np.ndarray, g: int) -> np.ndarray:
+        o = int(self.img_off[g])
+        return arr[o:o + int(self.h[g]) * int(self.w[g])].reshape(int(self.h[g]), int(self.w[g]))
+
+    def psf_of(self, g: int) -> np.ndarray:
+        k = int(self.psf_k[g])
+        o = int(self.psf_off[g])
+        return self.psf[o:o + k * k].reshape(k, k)
+
+    def subset(self, sel) -> "Batch":
+        """A new batch holding galaxies `sel` (data copied if present)."""
+        sel = np.asarray(sel, dtype=np.int64)
+        h, w, k = self.h[sel], self.w[sel], self.psf_k[sel]
+        img_off = np.concatenate([[0], np.cumsum(h.astype(np.int64) * w)[:-1]]).astype(np.int64)
+        psf_off = np.concatenate([[0], np.cumsum(k.astype(np.int64) * k)[:-1]]).astype(np.int64)
+        psf = np.concatenate([self.psf_of(int(g)).ravel() for g in sel]) if len(sel) else np.zeros(0, np.float32)
+        out = Batch(self.config, self.model, h.copy(), w.copy(), img_off, k.copy(), psf_off, psf,
+                    self.truth[sel].copy(), self.snr[sel].copy(), self.sky[sel].copy(), self.index[sel].copy(),
+                    self.seed)
+        if self.data is not None:
+            out.data = np.concatenate([self.image(self.data, int(g)).ravel() for g in sel])
+            out.sigma = np.concatenate([self.image(self.sigma, int(g)).ravel() for g in sel])
+        return out
+
+
+def _mag_columns(model: str) -> List[int]:
+    spec = MODEL_SPECS[model]
+    cols = []
+    for typ, _conv, idx, _fx in spec["comps"]:
+        if typ in (SERSIC, EXPDISK, FERRER, MOFFAT):
+            cols.append(idx[2])
+    return cols
+
+
+def _sersic_draw(r: np.random.Generator, h: int, w: int):
+    x0 = w / 2.0 + r.uniform(-2.0, 2.0)
+    y0 = h / 2.0 + r.uniform(-2.0, 2.0)
+    re = math.exp(r.uniform(math.log(2.0), math.log(15.0)))
+    n = r.uniform(0.5, 6.0)
+    q = r.uniform(0.3, 1.0)
+    pa = r.uniform(0.0, 180.0)
+    snr = math.exp(r.uniform(math.log(20.0), math.log(200.0)))
+    return x0, y0, re, n, q, pa, snr
+
+
+def draw(config: str, n: int, seed: int = 0, start: int = 0) -> Batch:
+    """Draw galaxies start..start+n-1 of a workload (no images yet)."""
+    cfg = CONFIG_IDS[config]
+    hs, ws, ks, psfs, truths, snrs, skies = [], [], [], [], [], [], []
+    model = "bulgedisk" if config == "bulgedisk" else "sersic"
+    p = MODEL_SPECS[model]["p"]
+    gpsf = gaussian_psf(1.5, 15) if config == "sersic64" else None
+    for i in range(start, start + n):
+        r = _rng(seed, cfg, i, 0)
+        t = np.zeros(p)
+        if config == "sersic64":
+            h = w = 64
+            x0, y0, re, nn, q, pa, snr = _sersic_draw(r, h, w)
+            sky = r.uniform(0.5, 1.5)
+            psf = gpsf
+            t[:] = [x0, y0, M0, re, nn, q, pa, sky]
+        elif config == "uneven":
+            side = int(round(math.exp(r.uniform(math.log(48.0), math.log(256.0)))))
+            h = w = side
+            x0, y0, re, nn, q, pa, snr = _sersic_draw(r, h, w)
+            beta = r.uniform(2.5, 4.5)
+            fwhm = r.uniform(1.2, 2.5)
+            sky = r.uniform(50.0, 200.0)
+            psf = moffat_psf(beta, fwhm, 25)
+            t[:] = [x0, y0, M0, re, nn, q, pa, sky]
+        elif config == "bulgedisk":
+            h = w = 128
+            x0 = w / 2.0 + r.uniform(-2.0, 2.0)
+            y0 = h / 2.0 + r.uniform(-2.0, 2.0)
+            n_b = r.uniform(2.0, 6.0)
+            re_b = math.exp(r.uniform(math.log(1.0), math.log(6.0)))
+            q_b = r.uniform(0.5, 1.0)
+            pa_b = r.uniform(0.0, 180.0)
+            re_d = math.exp(r.uniform(math.log(5.0), math.log(25.0)))
+            q_d = r.uniform(0.2, 1.0)
+            pa_d = r.uniform(0.0, 180.0)
+            bt = r.uniform(0.1, 0.9)
+            snr = math.exp(r.uniform(math.log(20.0), math.log(200.0)))
+            beta = r.uniform(2.5, 4.5)
+            fwhm = r.uniform(1.2, 2.5)
+            sky = r.uniform(50.0, 200.0)
+            psf = moffat_psf(beta, fwhm, 25)
+            # magnitudes encode the bulge-to-total split of a unit total flux
+            m_b = M0 - 2.5 * math.log10(bt)
+            m_d = M0 - 2.5 * math.log10(1.0 - bt)
+            t[:] = [x0, y0, m_b, re_b, n_b, q_b, pa_b, m_d, re_d / 1.678346990016661, q_d, pa_d, sky]
+        else:
+            raise ValueError(config)
+        hs.append(h)
+        ws.append(w)
+        ks.append(psf.shape[0])
+        psfs.append(psf.ravel())
+        truths.append(t)
+        snrs.append(snr)
+        skies.append(sky)
+    h = np.array(hs, np.int32)
+    w = np.array(ws, np.int32)
+    k = np.array(ks, np.int32)
+    img_off = np.concatenate([[0], np.cumsum(h.astype(np.int64) * w)[:-1]]).astype(np.int64)
+    psf_off = np.concatenate([[0], np.cumsum(k.astype(np.int64) * k)[:-1]]).astype(np.int64)
+    return Batch(config, model, h, w, img_off, k, psf_off, np.concatenate(psfs).astype(np.float32),
+                 np.array(truths), np.array(snrs), np.array(skies), np.arange(start, start + n, dtype=np.int64),
+                 seed)
+
+
+def unit_truth(b: Batch) -> np.ndarray:
+    """Parameters to render for finish(): total flux 1 (m = M0 split by the
+    drawn bulge fraction for two-component models) and zero sky."""
+    t = b.truth.copy()
+    spec = MODEL_SPECS[b.model]
+    for typ, _conv, idx, _fx in spec["comps"]:
+        if typ == SKY:
+            t[:, idx[0]] = 0.0
+    return t
+
+
+def finish(b: Batch, unit_images: np.ndarray) -> Batch:
+    """Scale unit-flux noiseless renders to the drawn peak SNR, add sky and
+    noise.  unit_images: concatenated float64/float32 pixels of the model
+    rendered at unit_truth(b).  Fills b.data, b.sigma and the magnitudes of
+    b.truth."""
+    cfg = CONFIG_IDS[b.config]
+    data = np.empty(b.npix, np.float32)
+    sigma = np.empty(b.npix, np.float32)
+    mag_cols = _mag_columns(b.model)
+    for g in range(b.n):
+        u = np.asarray(b.image(unit_images, g), np.float64)
+        peak = float(u.max())
+        if not peak > 0.0:
+            raise ValueError(f"galaxy {g}: non-positive unit render")
+        snr, sky = float(b.snr[g]), float(b.sky[g])
+        r = _rng(b.seed, cfg, int(b.index[g]), 1)
+        if b.config == "sersic64":
+            F = snr * 1.0 / peak
+            m_true = F * u + sky
+            d = m_true + r.standard_normal(u.shape)
+            s = np.ones_like(u)
+        else:
+            var0 = sky + READ_NOISE ** 2
+            P = 0.5 * (snr * snr + math.sqrt(snr ** 4 + 4.0 * snr * snr * var0))
+            F = P / peak
+            m_true = F * u + sky
+            d = r.poisson(m_true).astype(np.float64) + r.normal(0.0, READ_NOISE, u.shape)
+            s = np.sqrt(m_true + READ_NOISE ** 2)
+        o = int(b.img_off[g])
+        npx = u.size
+        data[o:o + npx] = d.ravel()
+        sigma[o:o + npx] = s.ravel()
+        for c in mag_cols:
+            b.truth[g, c] = b.truth[g, c] - 2.5 * math.log10(F)
+    b.data = data
+    b.sigma = sigma
+    return b

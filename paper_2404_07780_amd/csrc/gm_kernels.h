@@ -1,0 +1,871 @@
+// gm_kernels.hip -- gfx950 kernels of libgmfit.
+//
+// Work decomposition.  A galaxy's cutout is processed in 32 x 32 output tiles
+// by one 256-thread workgroup.  For a tile, the profile value and the
+// derivative of the light with respect to every LM variable are evaluated
+// (FP32) on the tile's (32 + K - 1)^2 input region straight into LDS, one
+// plane per quantity; the oversampled central window is evaluated once per
+// model evaluation into a small LDS table.  Each thread then convolves a 1 x 4
+// strip of outputs of every plane with the PSF (true convolution, zero
+// padding), streaming a (K + 3)-float row segment from LDS per PSF row and
+// reading the PSF through the scalar cache, and keeps the 4 x planes results
+// in registers.  The fitting kernel turns them into residuals and FP64
+// normal-equation sums without writing any image to memory.
+//
+// gm_fit_batch runs one persistent kernel: each workgroup pulls galaxies, in
+// descending-cost order, from an atomic queue and runs the whole
+// Levenberg-Marquardt iteration for a galaxy; thread 0 does the FP64 damped
+// Cholesky solve and accept/reject between evaluations.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gm_device.h"
+
+namespace gm {
+
+constexpr int TILE = 32;
+constexpr int NT = 256;
+constexpr int NWAVE = NT / 64;
+constexpr int MAXP = 16;
+constexpr int MAXWIN = 25;      // oversampled window of at most 5 x 5 pixels
+
+struct Meta {
+    int32_t h, w, k, pad;
+    int64_t img_off, psf_off;
+};
+
+// Model description passed by value: internal LM index -> column of the
+// caller's parameter vector (-1: fixed at fixedv, natural units).
+struct ModelArgs {
+    int p;
+    int col[MAXP];
+    double fixedv[MAXP];
+    double m0;
+    int osf, osw;
+};
+
+struct BatchArgs {
+    const Meta *meta;
+    const float *data, *sigma, *psf;
+    const uint8_t *omega;
+};
+
+__device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Input-region geometry of a tile for PSF side K.
+__host__ __device__ inline int seg_vec4(int K) { return (K + 3 + 3) / 4; }
+__host__ __device__ inline int region_h(int K) { return TILE + K - 1; }
+__host__ __device__ inline int region_wp(int K) { return 28 + 4 * seg_vec4(K); }
+
+template <class F>
+__host__ __device__ inline size_t planes_bytes(int K)
+{
+    return (size_t)F::NPL * region_h(K) * region_wp(K) * sizeof(float);
+}
+
+// ---------------------------------------------------------------- per-evaluation state in LDS
+template <class F>
+struct EvalShared {
+    typename F::Prep prep;
+    float win[F::NCOMP][MAXWIN][F::NWV];
+};
+
+// Scalar prologue + oversampled window tables.  u: LDS (FP64, internal).
+// scratch: LDS float area of at least MAXWIN * osf * NWV floats.
+template <class F>
+__device__ void eval_prologue(const double *u, const ModelArgs &ma, int H, int W, EvalShared<F> &sh, float *scratch)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) F::prep(u, ma.m0, H, W, ma.osf, ma.osw, sh.prep);
+    __syncthreads();
+    const int f = ma.osf;
+    const float invf = 1.0f / (float)f;
+#pragma unroll 1
+    for (int c = 0; c < F::NCOMP; ++c) {
+        const Geo &g = F::geo(sh.prep, c);
+        const int ww = g.wj1 - g.wj0 + 1, wh = g.wi1 - g.wi0 + 1;
+        if (ww <= 0 || wh <= 0) continue;
+        const int nwin = ww * wh, items = nwin * f;
+        // each item: one sub-row (t) of one window pixel, summed over s
+        for (int it = tid; it < items; it += NT) {
+            int pix = it / f, t = it - pix * f;
+            int i = g.wi0 + pix / ww, j = g.wj0 + pix % ww;
+            float acc[F::NWV];
+#pragma unroll
+            for (int q = 0; q < F::NWV; ++q) acc[q] = 0.0f;
+            float ys = ((float)t + 0.5f) * invf;
+            for (int s = 0; s < f; ++s) {
+                float xs = ((float)s + 0.5f) * invf, dx, dy, v[F::NWV];
+                offsets(g, (float)j, xs, (float)(H - i), ys, dx, dy);
+                F::comp_pt(sh.prep, c, dx, dy, v);
+#pragma unroll
+                for (int q = 0; q < F::NWV; ++q) acc[q] += v[q];
+            }
+#pragma unroll
+            for (int q = 0; q < F::NWV; ++q) scratch[it * F::NWV + q] = acc[q];
+        }
+        __syncthreads();
+        const float norm = 1.0f / (float)(f * f);
+        for (int pix = tid; pix < nwin; pix += NT) {
+#pragma unroll
+            for (int q = 0; q < F::NWV; ++q) {
+                float s = 0.0f;
+                for (int t = 0; t < f; ++t) s += scratch[(pix * f + t) * F::NWV + q];
+                sh.win[c][pix][q] = s * norm;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Plane vector (light + derivatives) of the convolved components at pixel (i, j).
+template <class F>
+__device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, float *pl)
+{
+#pragma unroll
+    for (int q = 0; q < F::NPL; ++q) pl[q] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < F::NCOMP; ++c) {
+        const Geo &g = F::geo(sh.prep, c);
+        float v[F::NWV];
+        if (i >= g.wi0 && i <= g.wi1 && j >= g.wj0 && j <= g.wj1) {
+            const float *t = sh.win[c][(i - g.wi0) * (g.wj1 - g.wj0 + 1) + (j - g.wj0)];
+#pragma unroll
+            for (int q = 0; q < F::NWV; ++q) v[q] = t[q];
+        } else {
+            float dx, dy;
+            offsets(g, (float)j, 0.5f, (float)(H - i), 0.5f, dx, dy);
+            F::comp_pt(sh.prep, c, dx, dy, v);
+        }
+        F::scatter(c, v, pl);
+    }
+}
+
+// Fill the LDS planes of the input region of the tile at (ti0, tj0).
+template <class F>
+__device__ void fill_region(const EvalShared<F> &sh, float *planes, int H, int W, int K, int ti0, int tj0)
+{
+    const int IH = region_h(K), IWP = region_wp(K), IW = TILE + K - 1, c = (K - 1) / 2;
+    const int plane_sz = IH * IWP;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int ri = wave; ri < IH; ri += NWAVE) {
+        const int i = ti0 - c + ri;
+        for (int ci = lane; ci < IWP; ci += 64) {
+            const int j = tj0 - c + ci;
+            float pl[F::NPL];
+            if (ci < IW && i >= 0 && i < H && j >= 0 && j < W) {
+                planes_at<F>(sh, i, j, H, pl);
+            } else {
+#pragma unroll
+                for (int q = 0; q < F::NPL; ++q) pl[q] = 0.0f;
+            }
+            float *dst = planes + ri * IWP + ci;
+#pragma unroll
+            for (int q = 0; q < F::NPL; ++q) dst[q * plane_sz] = pl[q];
+        }
+    }
+}
+
+// Convolve every plane for this thread's 1 x 4 output strip (tile row r,
+// columns 4 cg .. 4 cg + 3).  KT > 0: compile-time PSF side; KT == 0: any K.
+template <class F, int KT>
+__device__ inline void conv_strip(const float *__restrict__ planes, int K, const float *__restrict__ psf, int r,
+                                  int cg, float (&acc)[F::NPL][4])
+{
+    const int IH = region_h(K), IWP = region_wp(K);
+    const int plane_sz = IH * IWP;
+    if constexpr (KT > 0) {
+        constexpr int NV4 = (KT + 3 + 3) / 4;
+#pragma unroll
+        for (int pl = 0; pl < F::NPL; ++pl) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            const float *base = planes + pl * plane_sz + 4 * cg;
+#pragma unroll 1
+            for (int u = 0; u < KT; ++u) {
+                const float4 *rp = reinterpret_cast<const float4 *>(base + (r + KT - 1 - u) * IWP);
+                float seg[NV4 * 4];
+#pragma unroll
+                for (int q = 0; q < NV4; ++q) {
+                    float4 t4 = rp[q];
+                    seg[4 * q] = t4.x;
+                    seg[4 * q + 1] = t4.y;
+                    seg[4 * q + 2] = t4.z;
+                    seg[4 * q + 3] = t4.w;
+                }
+                const float *pr = psf + u * KT;
+#pragma unroll
+                for (int v = 0; v < KT; ++v) {
+                    const float pv = pr[v];
+                    a0 = fmaf(pv, seg[KT - 1 - v], a0);
+                    a1 = fmaf(pv, seg[KT - v], a1);
+                    a2 = fmaf(pv, seg[KT + 1 - v], a2);
+                    a3 = fmaf(pv, seg[KT + 2 - v], a3);
+                }
+            }
+            acc[pl][0] = a0; acc[pl][1] = a1; acc[pl][2] = a2; acc[pl][3] = a3;
+        }
+    } else {
+#pragma unroll
+        for (int pl = 0; pl < F::NPL; ++pl) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            const float *base = planes + pl * plane_sz + 4 * cg;
+            for (int u = 0; u < K; ++u) {
+                const float *rp = base + (r + K - 1 - u) * IWP;
+                const float *pr = psf + u * K;
+                for (int v = 0; v < K; ++v) {
+                    const float pv = pr[v];
+                    const float *sp = rp + K - 1 - v;
+                    a0 = fmaf(pv, sp[0], a0);
+                    a1 = fmaf(pv, sp[1], a1);
+                    a2 = fmaf(pv, sp[2], a2);
+                    a3 = fmaf(pv, sp[3], a3);
+                }
+            }
+            acc[pl][0] = a0; acc[pl][1] = a1; acc[pl][2] = a2; acc[pl][3] = a3;
+        }
+    }
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
+{
+    d = ba.data[idx];
+    float s = ba.sigma[idx];
+    bool ok = (ba.omega == nullptr || ba.omega[idx] != 0) && s > 0.0f && isfinite(s) && isfinite(d);
+    return ok ? 1.0f / (s * s) : 0.0f;
+}
+
+// One model evaluation at u (LDS): chi^2, g = J^T W r and the lower triangle
+// of A = J^T W J (internal LM variables), written to out_chi2/out_g/out_A
+// (LDS, A full p x p).  All threads of the workgroup call it.
+template <class F, int KT>
+__device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &ba, const Meta &me, EvalShared<F> &sh,
+                         float *planes, double *out_chi2, double *out_g, double *out_A)
+{
+    constexpr int P = F::P;
+    constexpr int NR = 1 + P + P * (P + 1) / 2;
+    const int H = me.h, W = me.w, K = me.k;
+    const int tid = threadIdx.x;
+    eval_prologue<F>(u, ma, H, W, sh, planes);
+    const float sky = sh.prep.sky;
+    const float *psf = ba.psf + me.psf_off;
+    double red[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) red[q] = 0.0;
+    const int r = tid >> 3, cg = tid & 7;
+    const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
+    for (int ty = 0; ty < nty; ++ty) {
+        for (int tx = 0; tx < ntx; ++tx) {
+            const int ti0 = ty * TILE, tj0 = tx * TILE;
+            fill_region<F>(sh, planes, H, W, K, ti0, tj0);
+            __syncthreads();
+            float acc[F::NPL][4];
+            conv_strip<F, KT>(planes, K, psf, r, cg, acc);
+            __syncthreads();
+            const int i = ti0 + r;
+            if (i < H) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int j = tj0 + 4 * cg + t;
+                    if (j >= W) continue;
+                    const int64_t idx = me.img_off + (int64_t)i * W + j;
+                    float d;
+                    const float wgt = pixel_weight(ba, idx, d);
+                    if (wgt == 0.0f) continue;
+                    const double res = (double)(d - (acc[0][t] + sky));
+                    double J[P];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) J[k] = (k == F::SKY) ? 1.0 : (double)acc[1 + k][t];
+                    const double wr = (double)wgt * res;
+                    red[0] = fma(wr, res, red[0]);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) red[1 + k] = fma(wr, J[k], red[1 + k]);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        const double wj = (double)wgt * J[k];
+#pragma unroll
+                        for (int l = 0; l <= k; ++l)
+                            red[1 + P + k * (k + 1) / 2 + l] = fma(wj, J[l], red[1 + P + k * (k + 1) / 2 + l]);
+                    }
+                }
+            }
+        }
+    }
+    // fixed-order reduction: within each wave, then the waves in order
+    // (the planes are idle after the last tile's barrier: reuse them)
+    double *sred = reinterpret_cast<double *>(planes);
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double v = wave_sum(red[q]);
+        if (lane == 0) sred[wave * NR + q] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < NR; q += NT) {
+        double s = sred[q];
+        for (int wv = 1; wv < NWAVE; ++wv) s += sred[wv * NR + q];
+        if (q == 0) {
+            *out_chi2 = s;
+        } else if (q <= P) {
+            out_g[q - 1] = s;
+        } else {
+            int e = q - 1 - P, k = 0;
+            while ((k + 1) * (k + 2) / 2 <= e) ++k;
+            int l = e - k * (k + 1) / 2;
+            out_A[k * P + l] = s;
+            out_A[l * P + k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- small FP64 algebra (one thread)
+// Cholesky L L^T = M of a P x P matrix; returns false if not positive definite.
+template <int P>
+__device__ bool chol(const double *M, double *L)
+{
+    for (int i = 0; i < P * P; ++i) L[i] = 0.0;
+    for (int j = 0; j < P; ++j) {
+        double d = M[j * P + j];
+        for (int k = 0; k < j; ++k) d -= L[j * P + k] * L[j * P + k];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        double lj = sqrt(d);
+        L[j * P + j] = lj;
+        for (int i = j + 1; i < P; ++i) {
+            double s = M[i * P + j];
+            for (int k = 0; k < j; ++k) s -= L[i * P + k] * L[j * P + k];
+            L[i * P + j] = s / lj;
+        }
+    }
+    return true;
+}
+
+template <int P>
+__device__ void chol_solve(const double *L, const double *b, double *x)
+{
+    double y[P];
+    for (int i = 0; i < P; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * P + k] * y[k];
+        y[i] = s / L[i * P + i];
+    }
+    for (int i = P - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < P; ++k) s -= L[k * P + i] * x[k];
+        x[i] = s / L[i * P + i];
+    }
+}
+
+template <int P>
+__device__ void chol_inverse(const double *L, double *inv)
+{
+    for (int j = 0; j < P; ++j) {
+        double e[P], col[P];
+        for (int i = 0; i < P; ++i) e[i] = (i == j) ? 1.0 : 0.0;
+        chol_solve<P>(L, e, col);
+        for (int i = 0; i < P; ++i) inv[i * P + j] = col[i];
+    }
+}
+
+// Fixed parameters: their rows and columns of A are replaced by the identity
+// and their gradient by 0, so that they never move.
+template <int P>
+__device__ void project_fixed(const int *freev, double *A, double *g)
+{
+    for (int k = 0; k < P; ++k) {
+        if (freev[k]) continue;
+        for (int l = 0; l < P; ++l) {
+            A[k * P + l] = 0.0;
+            A[l * P + k] = 0.0;
+        }
+        A[k * P + k] = 1.0;
+        g[k] = 0.0;
+    }
+}
+
+// Bounds of the LM variables (natural units: centres inside the cutout,
+// scales in [0.1, 2 max(H, W)] px, Sersic n in [0.2, 10], q in [0.05, 20]).
+template <class F>
+__device__ void clamp_u(double *u, int H, int W)
+{
+    const double big = 2.0 * (H > W ? H : W);
+    for (int k = 0; k < F::P; ++k) {
+        double lo = -INFINITY, hi = INFINITY;
+        switch (F::kind(k)) {
+        case KX0: lo = 0.0; hi = W; break;
+        case KY0: lo = 0.0; hi = H; break;
+        case KSCALE: lo = log(0.1); hi = log(big); break;
+        case KN: lo = log(0.2); hi = log(10.0); break;
+        case KQ: lo = 0.05; hi = 20.0; break;
+        default: break;
+        }
+        u[k] = fmin(fmax(u[k], lo), hi);
+    }
+}
+
+// Canonical form of every component: q > 1 -> (1/q, scale * q, theta + pi/2),
+// then theta wrapped into [0, pi).  u in internal layout; natural output.
+template <class F>
+__device__ void canonical_nat(const double *u, const int *freev, double *nat)
+{
+    for (int k = 0; k < F::P; ++k) nat[k] = u_to_nat(F::kind(k), u[k]);
+    for (int c = 0; c < F::NCAN; ++c) {
+        int iq, ith, is0, is1;
+        F::canon(c, iq, ith, is0, is1);
+        if (freev[iq] && freev[ith] && nat[iq] > 1.0) {
+            double qo = nat[iq];
+            nat[iq] = 1.0 / qo;
+            if (is0 >= 0) nat[is0] *= qo;
+            if (is1 >= 0) nat[is1] *= qo;
+            nat[ith] += 90.0;
+        }
+        if (freev[ith]) {
+            double pa = fmod(nat[ith], 180.0);
+            if (pa < 0.0) pa += 180.0;
+            if (pa >= 180.0) pa -= 180.0;
+            nat[ith] = pa;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- LM kernel
+template <class F>
+struct LMShared {
+    double u[F::P], ut[F::P], g[F::P], gt[F::P], A[F::P * F::P], At[F::P * F::P];
+    double Dg[F::P], sig[F::P], delta[F::P];
+    double *M, *L, *inv;        // thread-0 temporaries in the (idle) plane buffer
+    double chi2, chi2t, lambda;
+    int freev[F::P];
+    int t, status, fresh, apd, action;
+    int gal;
+};
+
+struct FitArgs {
+    const int *order;
+    int n_gal;
+    int *queue;
+    double *params, *chi2;
+    int *niter, *status;
+    int max_iter;
+    double lambda0, tol;
+};
+
+enum { ACT_EVAL = 0, ACT_RETRY = 1, ACT_DONE = 2 };
+
+// Thread 0: choose the next trial point, or finish.
+template <class F>
+__device__ void lm_propose(LMShared<F> &s, const FitArgs &fa, int H, int W)
+{
+    constexpr int P = F::P;
+    if (s.t >= fa.max_iter) {
+        s.status = GM_ST_MAXITER;
+        s.action = ACT_DONE;
+        return;
+    }
+    s.t += 1;
+    if (s.fresh) {
+        double amax = 0.0;
+        for (int k = 0; k < P; ++k)
+            if (s.freev[k] && s.A[k * P + k] > amax) amax = s.A[k * P + k];
+        for (int k = 0; k < P; ++k) {
+            double d = s.A[k * P + k];
+            s.Dg[k] = s.freev[k] ? (d > 1e-12 * amax ? d : 1e-12 * amax) : 1.0;
+        }
+        s.apd = chol<P>(s.A, s.L);
+        if (s.apd) {
+            chol_inverse<P>(s.L, s.inv);
+            for (int k = 0; k < P; ++k) s.sig[k] = sqrt(s.inv[k * P + k]);
+            chol_solve<P>(s.L, s.g, s.delta);
+            double smax = 0.0;
+            for (int k = 0; k < P; ++k) {
+                double q = fabs(s.delta[k]) / s.sig[k];
+                if (!(q <= smax)) smax = q;
+            }
+            if (smax < fa.tol) {
+                s.t -= 1;
+                s.status = GM_ST_CONVERGED;
+                s.action = ACT_DONE;
+                return;
+            }
+        } else {
+            for (int k = 0; k < P; ++k) s.sig[k] = 1.0 / sqrt(s.Dg[k]);
+        }
+        s.fresh = 0;
+    }
+    for (int a = 0; a < P; ++a)
+        for (int b = 0; b < P; ++b) s.M[a * P + b] = s.A[a * P + b] + (a == b ? s.lambda * s.Dg[a] : 0.0);
+    if (!chol<P>(s.M, s.L)) {
+        s.lambda *= 10.0;
+        if (s.lambda > 1e9) {
+            s.status = GM_ST_STALLED;
+            s.action = ACT_DONE;
+        } else {
+            s.action = ACT_RETRY;
+        }
+        return;
+    }
+    chol_solve<P>(s.L, s.g, s.delta);
+    if (!s.apd) {
+        double smax = 0.0;
+        for (int k = 0; k < P; ++k) {
+            double q = fabs(s.delta[k]) / s.sig[k];
+            if (!(q <= smax)) smax = q;
+        }
+        if (smax < fa.tol) {
+            s.t -= 1;
+            s.status = GM_ST_CONVERGED;
+            s.action = ACT_DONE;
+            return;
+        }
+    }
+    for (int k = 0; k < P; ++k) s.ut[k] = s.u[k] + (s.freev[k] ? s.delta[k] : 0.0);
+    clamp_u<F>(s.ut, H, W);
+    s.action = ACT_EVAL;
+}
+
+template <class F>
+__device__ void lm_accept(LMShared<F> &s)
+{
+    constexpr int P = F::P;
+    project_fixed<P>(s.freev, s.At, s.gt);
+    if (isfinite(s.chi2t) && s.chi2t < s.chi2) {
+        for (int k = 0; k < P; ++k) {
+            s.u[k] = s.ut[k];
+            s.g[k] = s.gt[k];
+        }
+        for (int k = 0; k < P * P; ++k) s.A[k] = s.At[k];
+        s.chi2 = s.chi2t;
+        s.lambda = fmax(s.lambda / 10.0, 1e-9);
+        s.fresh = 1;
+    } else {
+        s.lambda *= 10.0;
+        if (s.lambda > 1e9) {
+            s.status = GM_ST_STALLED;
+            s.action = ACT_DONE;
+        }
+    }
+}
+
+template <class F>
+__device__ void load_u(LMShared<F> &s, const ModelArgs &ma, const double *params)
+{
+    for (int k = 0; k < F::P; ++k) {
+        int c = ma.col[k];
+        double nat = c >= 0 ? params[c] : ma.fixedv[k];
+        s.u[k] = nat_to_u(F::kind(k), nat);
+        s.freev[k] = c >= 0;
+    }
+}
+
+template <class F, int KT>
+__global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, FitArgs fa)
+{
+    extern __shared__ float4 dyn_lds[];
+    float *planes = reinterpret_cast<float *>(dyn_lds);
+    __shared__ EvalShared<F> esh;
+    __shared__ LMShared<F> s;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s.gal = atomicAdd(fa.queue, 1);
+        __syncthreads();
+        const int qi = uniform(s.gal);
+        if (qi >= fa.n_gal) break;
+        const int g = uniform(fa.order[qi]);
+        const Meta me = ba.meta[g];
+        if (tid == 0) {
+            double *tmp = reinterpret_cast<double *>(planes);
+            s.M = tmp;
+            s.L = tmp + F::P * F::P;
+            s.inv = tmp + 2 * F::P * F::P;
+            load_u<F>(s, ma, fa.params + (int64_t)g * ma.p);
+            clamp_u<F>(s.u, me.h, me.w);
+            s.t = 0;
+            s.status = GM_ST_MAXITER;
+            s.lambda = fa.lambda0;
+            s.fresh = 1;
+            s.action = ACT_EVAL;
+        }
+        __syncthreads();
+        evaluate<F, KT>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
+        if (tid == 0) {
+            project_fixed<F::P>(s.freev, s.A, s.g);
+            if (!isfinite(s.chi2)) {
+                s.status = GM_ST_NONFINITE;
+                s.action = ACT_DONE;
+            } else {
+                s.action = ACT_EVAL;
+            }
+        }
+        __syncthreads();
+        while (s.action != ACT_DONE) {
+            if (tid == 0) lm_propose<F>(s, fa, me.h, me.w);
+            __syncthreads();
+            const int act = s.action;
+            if (act == ACT_EVAL) {
+                evaluate<F, KT>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
+                if (tid == 0) lm_accept<F>(s);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double nat[F::P];
+            canonical_nat<F>(s.u, s.freev, nat);
+            double *out = fa.params + (int64_t)g * ma.p;
+            for (int k = 0; k < F::P; ++k)
+                if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
+            fa.chi2[g] = s.chi2;
+            fa.niter[g] = s.t;
+            fa.status[g] = s.status;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- covariance errors
+struct ErrArgs {
+    const double *params;
+    double *err, *cov;
+    int n_gal;
+};
+
+template <class F, int KT>
+__global__ __launch_bounds__(NT) void errors_kernel(ModelArgs ma, BatchArgs ba, ErrArgs ea)
+{
+    extern __shared__ float4 dyn_lds[];
+    float *planes = reinterpret_cast<float *>(dyn_lds);
+    __shared__ EvalShared<F> esh;
+    __shared__ LMShared<F> s;
+    constexpr int P = F::P;
+    const int tid = threadIdx.x;
+    for (int g = blockIdx.x; g < ea.n_gal; g += gridDim.x) {
+        const Meta me = ba.meta[g];
+        if (tid == 0) load_u<F>(s, ma, ea.params + (int64_t)g * ma.p);
+        __syncthreads();
+        evaluate<F, KT>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
+        if (tid == 0) {
+            double *tmp = reinterpret_cast<double *>(planes);
+            s.L = tmp;
+            s.inv = tmp + P * P;
+            project_fixed<P>(s.freev, s.A, s.g);
+            const int p = ma.p;
+            double *err = ea.err + (int64_t)g * p;
+            double *cov = ea.cov ? ea.cov + (int64_t)g * p * p : nullptr;
+            if (chol<P>(s.A, s.L)) {
+                chol_inverse<P>(s.L, s.inv);
+                for (int a = 0; a < P; ++a) {
+                    if (ma.col[a] < 0) continue;
+                    double na = u_to_nat(F::kind(a), s.u[a]);
+                    double sa = dnat_du(F::kind(a), na);
+                    err[ma.col[a]] = sqrt(s.inv[a * P + a]) * fabs(sa);
+                    if (cov)
+                        for (int b = 0; b < P; ++b) {
+                            if (ma.col[b] < 0) continue;
+                            double nb = u_to_nat(F::kind(b), s.u[b]);
+                            cov[ma.col[a] * p + ma.col[b]] = sa * s.inv[a * P + b] * dnat_du(F::kind(b), nb);
+                        }
+                }
+            } else {
+                for (int a = 0; a < p; ++a) err[a] = NAN;
+                if (cov)
+                    for (int a = 0; a < p * p; ++a) cov[a] = NAN;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- model image / Jacobian
+struct TileItem {
+    int32_t gal, ty, tx, pad;
+};
+
+struct ImageArgs {
+    const TileItem *tiles;
+    int n_tiles;
+    const double *params;
+    float *out;      // model (mode 0) or Jacobian (mode 1)
+    int mode;
+};
+
+template <class F, int KT>
+__global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, ImageArgs ia)
+{
+    extern __shared__ float4 dyn_lds[];
+    float *planes = reinterpret_cast<float *>(dyn_lds);
+    __shared__ EvalShared<F> esh;
+    __shared__ double su[F::P];
+    __shared__ int sfree[F::P];
+    constexpr int P = F::P;
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < ia.n_tiles; it += gridDim.x) {
+        const TileItem ti = ia.tiles[it];
+        const int g = uniform(ti.gal);
+        const Meta me = ba.meta[g];
+        const int H = me.h, W = me.w, K = me.k;
+        if (tid == 0) {
+            const double *pp = ia.params + (int64_t)g * ma.p;
+            for (int k = 0; k < P; ++k) {
+                int c = ma.col[k];
+                su[k] = nat_to_u(F::kind(k), c >= 0 ? pp[c] : ma.fixedv[k]);
+                sfree[k] = c >= 0;
+            }
+        }
+        __syncthreads();
+        eval_prologue<F>(su, ma, H, W, esh, planes);
+        const int ti0 = ti.ty * TILE, tj0 = ti.tx * TILE;
+        fill_region<F>(esh, planes, H, W, K, ti0, tj0);
+        __syncthreads();
+        const int r = tid >> 3, cg = tid & 7;
+        float acc[F::NPL][4];
+        conv_strip<F, KT>(planes, K, ba.psf + me.psf_off, r, cg, acc);
+        const int i = ti0 + r;
+        if (i < H) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = tj0 + 4 * cg + t;
+                if (j >= W) continue;
+                const int64_t pix = (int64_t)i * W + j;
+                if (ia.mode == 0) {
+                    ia.out[me.img_off + pix] = acc[0][t] + esh.prep.sky;
+                } else {
+                    float *jo = ia.out + (int64_t)ma.p * me.img_off;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        if (!sfree[k]) continue;
+                        float du_dp = (float)(1.0 / dnat_du(F::kind(k), u_to_nat(F::kind(k), su[k])));
+                        float jv = (k == F::SKY) ? 1.0f : acc[1 + k][t];
+                        jo[(int64_t)ma.col[k] * H * W + pix] = jv * du_dp;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- default guess
+struct GuessArgs {
+    double *params, *moments;
+    int n_gal;
+};
+
+__device__ inline double block_sum(double v, double *sred)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sred[wave] = v;
+    __syncthreads();
+    double s = sred[0];
+    for (int w = 1; w < NWAVE; ++w) s += sred[w];
+    return s;
+}
+
+// Moments: sky0 = mean of usable pixels in the 2-px frame; S = usable pixels
+// with D - sky0 > 3 sigma; flux, flux-weighted centroid and central second
+// moments over S.  Start vector per family (see host documentation).
+template <class F>
+__global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, GuessArgs ga)
+{
+    __shared__ double sred[NWAVE];
+    const int tid = threadIdx.x;
+    for (int g = blockIdx.x; g < ga.n_gal; g += gridDim.x) {
+        const Meta me = ba.meta[g];
+        const int H = me.h, W = me.w;
+        const int64_t npix = (int64_t)H * W;
+        double ss = 0.0, sc = 0.0;
+        for (int64_t q = tid; q < npix; q += NT) {
+            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+            if (!(i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) continue;
+            float d;
+            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+            ss += d;
+            sc += 1.0;
+        }
+        ss = block_sum(ss, sred);
+        sc = block_sum(sc, sred);
+        const double sky0 = sc > 0.0 ? ss / sc : 0.0;
+        double f0 = 0.0, fx = 0.0, fy = 0.0, cnt = 0.0, pk = 0.0;
+        for (int64_t q = tid; q < npix; q += NT) {
+            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+            float d;
+            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+            double dp = (double)d - sky0;
+            if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
+            double x = j + 0.5, y = (double)H - i - 0.5;
+            f0 += dp; fx += dp * x; fy += dp * y; cnt += 1.0;
+            pk = fmax(pk, dp);
+        }
+        f0 = block_sum(f0, sred);
+        fx = block_sum(fx, sred);
+        fy = block_sum(fy, sred);
+        cnt = block_sum(cnt, sred);
+        // block max of the peak
+        {
+            const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) pk = fmax(pk, __shfl_xor(pk, o, 64));
+            __syncthreads();
+            if (lane == 0) sred[wave] = pk;
+            __syncthreads();
+            pk = sred[0];
+            for (int w = 1; w < NWAVE; ++w) pk = fmax(pk, sred[w]);
+        }
+        double xc = 0.5 * W, yc = 0.5 * H, r0 = 3.0, q0 = 1.0, th0 = 0.0;
+        const bool have = cnt >= 5.0 && f0 > 0.0;
+        double mxx = 0.0, myy = 0.0, mxy = 0.0;
+        if (have) {
+            xc = fx / f0;
+            yc = fy / f0;
+            for (int64_t q = tid; q < npix; q += NT) {
+                int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+                float d;
+                if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+                double dp = (double)d - sky0;
+                if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
+                double dx = j + 0.5 - xc, dy = (double)H - i - 0.5 - yc;
+                mxx += dp * dx * dx; myy += dp * dy * dy; mxy += dp * dx * dy;
+            }
+        }
+        mxx = block_sum(mxx, sred);
+        myy = block_sum(myy, sred);
+        mxy = block_sum(mxy, sred);
+        if (tid == 0) {
+            if (have) {
+                mxx /= f0; myy /= f0; mxy /= f0;
+                double tr = 0.5 * (mxx + myy), dd = sqrt(0.25 * (mxx - myy) * (mxx - myy) + mxy * mxy);
+                double lp = tr + dd, lm = fmax(tr - dd, 0.0);
+                q0 = lp > 0.0 ? sqrt(lm / lp) : 1.0;
+                q0 = fmin(fmax(q0, 0.1), 1.0);
+                th0 = 0.5 * atan2(2.0 * mxy, mxx - myy);
+                r0 = 1.1774 * sqrt(fmax(lp, 0.0));
+                r0 = fmin(fmax(r0, 1.0), 0.25 * W);
+            }
+            double mg = ma.m0 - 2.5 * log10(fmax(f0, 1e-3));
+            double pa0 = th0 * 180.0 / kPi;
+            if (pa0 < 0.0) pa0 += 180.0;
+            if (ga.moments) {
+                double *mo = ga.moments + (int64_t)g * 6;
+                mo[0] = xc - 0.5 * W; mo[1] = yc - 0.5 * H; mo[2] = mg;
+                mo[3] = log(r0); mo[4] = q0; mo[5] = th0;
+            }
+            double nat[F::P];
+            F::default_guess(xc, yc, mg, r0, q0, pa0, sky0, pk > 0.0 ? pk : 1.0, nat);
+            double *out = ga.params + (int64_t)g * ma.p;
+            for (int k = 0; k < F::P; ++k)
+                if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void fill_int_kernel(int *p, int v) { *p = v; }
+
+}  // namespace gm

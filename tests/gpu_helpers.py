@@ -1,0 +1,56 @@
+"""Test-side helpers: synthetic batches whose images are rendered by the FP64
+oracle (so no oracle input ever comes from the HIP path), and the parity
+metrics of the fitted quantities."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+from paper_2404_07780_amd import synth as S
+from tests.oracle_models import from_spec
+
+
+def oracle_batch(config: str, n: int, seed: int = 0, start: int = 0) -> S.Batch:
+    """Draw n galaxies and render their unit-flux images with the oracle."""
+    b = S.draw(config, n, seed=seed, start=start)
+    m = from_spec(b.model)
+    ut = S.unit_truth(b)
+    units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
+                            for g in range(b.n)])
+    return S.finish(b, units)
+
+
+def image_parity(gpu: np.ndarray, ref: np.ndarray, rel: float = 1e-5, floor: float = 1e-6):
+    """|M_gpu - M_or| <= rel * max(|M_or|, floor * max|M_or|) per pixel; returns
+    (ok, worst ratio)."""
+    scale = np.maximum(np.abs(ref), floor * np.max(np.abs(ref)))
+    ratio = np.abs(gpu - ref) / (rel * scale)
+    return bool(np.all(ratio <= 1.0)), float(np.max(ratio))
+
+
+# floors of the parameter parity metric per parameter kind (natural units)
+FLOORS = {"x0": 1.0, "y0": 1.0, "re": 0.1, "rs": 0.1, "n": 0.1, "q": 0.01, "sky": 1.0}
+
+
+def param_parity(names, gpu, ref, sky_sigma: float = 1.0, rel: float = 1e-4):
+    """Per-parameter pass flags: |dp| <= rel * max(|p_ref|, floor); position
+    angles compared modulo 180 deg with a 1 rad floor; magnitudes through flux
+    (|dF/F| <= rel)."""
+    ok = np.ones(len(names), bool)
+    worst = np.zeros(len(names))
+    for k, nm in enumerate(names):
+        a, b = float(gpu[k]), float(ref[k])
+        if nm.startswith("pa"):
+            d = (a - b + 90.0) % 180.0 - 90.0
+            r = abs(math.radians(d)) / (rel * max(abs(math.radians(b)), 1.0))
+        elif nm.startswith("mag"):
+            r = abs(10 ** (-0.4 * (a - b)) - 1.0) / rel
+        else:
+            base = nm.split("_")[0]
+            fl = sky_sigma if base == "sky" else FLOORS.get(base, 0.0)
+            r = abs(a - b) / (rel * max(abs(b), fl))
+        worst[k] = r
+        ok[k] = r <= 1.0
+    return ok, worst

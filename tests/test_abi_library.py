@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmfit.h")
+LIB = os.path.join(ROOT, "paper_2404_07780_amd", "lib", "libgmfit.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(gm_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2404_07780_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian", "gm_fit_batch",
+              "gm_param_errors", "gm_default_guess"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    for n in declared():
+        assert n in exported, n
+
+
+def test_binding_lists_every_symbol():
+    from paper_2404_07780_amd import gmfit
+
+    assert sorted(gmfit.SYMBOLS) == declared()
+
+
+def test_error_strings(lib):
+    lib.gm_error_string.restype = ctypes.c_char_p
+    lib.gm_error_string.argtypes = [ctypes.c_int]
+    assert lib.gm_error_string(0) == b"success"
+    assert b"invalid" in lib.gm_error_string(-1)
+    assert lib.gm_error_string(-99) == b"unknown error"

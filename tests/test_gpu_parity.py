@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: model images 1e-5 relative per pixel (floor 1e-6 of the image
+maximum), Jacobian columns 1e-5 of the column maximum, fitted parameters 1e-4
+relative from the same start vector (floors in tests/gpu_helpers.py), moments
+1e-6 relative, covariance errors 1e-4 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle as O
+from paper_2404_07780_amd import gmfit as G
+from paper_2404_07780_amd import synth as S
+from tests.gpu_helpers import image_parity, oracle_batch, param_parity
+from tests.oracle_models import from_spec
+
+
+def _dev_batch(b: S.Batch, omega=None) -> G.Batch:
+    return G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf, omega=omega)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    print("building sersic64 galaxies 0..63 (seed 0)", flush=True)
+    return oracle_batch("sersic64", 64, seed=0)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    print("building uneven galaxies 0..11 (seed 0)", flush=True)
+    return oracle_batch("uneven", 12, seed=0)
+
+
+def _model_parity(b: S.Batch, params):
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    db = _dev_batch(b)
+    out = G.gm_model_image(gm, db, params).cpu().numpy()
+    worst = 0.0
+    for g in range(b.n):
+        ref = O.model_image(om, int(b.h[g]), int(b.w[g]), b.psf_of(g), params[g])
+        ok, w = image_parity(b.image(out, g), ref)
+        worst = max(worst, w)
+        assert ok, f"galaxy {g} ({b.h[g]}x{b.w[g]}): worst ratio {w}"
+    return worst
+
+
+def test_model_image_sersic64(cfg1):
+    print("model image parity, sersic64", flush=True)
+    _model_parity(cfg1, cfg1.truth)
+
+
+def test_model_image_uneven_sizes(cfg2):
+    print("model image parity, uneven 48-256 px, K=25", flush=True)
+    _model_parity(cfg2, cfg2.truth)
+
+
+def test_model_image_bulge_disk():
+    print("model image parity, bulgedisk 128 px, 12 planes", flush=True)
+    b = oracle_batch("bulgedisk", 4, seed=0)
+    _model_parity(b, b.truth)
+
+
+def test_model_image_small_and_ragged():
+    # cutouts smaller than a tile, non-square, centres near the border (clipped windows)
+    rng = np.random.default_rng(7)
+    hs = np.array([1, 7, 33, 40, 65, 20], np.int32)
+    ws = np.array([1, 9, 31, 70, 33, 64], np.int32)
+    n = len(hs)
+    psf = np.concatenate([S.gaussian_psf(1.8, 15).ravel()] * n)
+    params = []
+    for g in range(n):
+        params.append([rng.uniform(0, ws[g]), rng.uniform(0, hs[g]), 18.0, rng.uniform(1, 6), rng.uniform(0.6, 5),
+                       rng.uniform(0.3, 1.0), rng.uniform(0, 180), 1.0])
+    params = np.array(params)
+    params[1, :2] = [0.3, 8.7]          # window clipped at the corner
+    img_off = np.concatenate([[0], np.cumsum(hs.astype(np.int64) * ws)[:-1]])
+    b = S.Batch("sersic64", "sersic", hs, ws, img_off, np.full(n, 15, np.int32),
+                np.arange(n, dtype=np.int64) * 225, psf.astype(np.float32), params, np.ones(n), np.ones(n),
+                np.arange(n))
+    b.data = np.zeros(b.npix, np.float32)
+    b.sigma = np.ones(b.npix, np.float32)
+    _model_parity(b, params)
+
+
+def test_model_image_generic_psf_size():
+    # a PSF side without a compile-time kernel (K = 9) takes the generic path
+    b = oracle_batch("sersic64", 3, seed=5)
+    k = 9
+    psf = S.moffat_psf(3.0, 2.0, k)
+    b.psf = np.concatenate([psf.ravel()] * b.n)
+    b.psf_k = np.full(b.n, k, np.int32)
+    b.psf_off = np.arange(b.n, dtype=np.int64) * k * k
+    _model_parity(b, b.truth)
+
+
+def test_jacobian_sersic64(cfg1):
+    print("jacobian parity, sersic64 galaxies 0..15", flush=True)
+    b = cfg1.subset(range(16))
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    jac = G.gm_jacobian(gm, _dev_batch(b), b.truth).cpu().numpy()
+    p = gm.p
+    for g in range(b.n):
+        h, w = int(b.h[g]), int(b.w[g])
+        ref = O.jacobian(om, h, w, b.psf_of(g), b.truth[g])
+        got = jac[p * int(b.img_off[g]): p * int(b.img_off[g]) + p * h * w].reshape(p, h, w)
+        for k in range(p):
+            err = np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k]))
+            assert err <= 1e-5, (g, k, err)
+
+
+def test_jacobian_bulge_disk_uneven():
+    b = oracle_batch("bulgedisk", 2, seed=3)
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    jac = G.gm_jacobian(gm, _dev_batch(b), b.truth).cpu().numpy()
+    p = gm.p
+    for g in range(b.n):
+        h, w = int(b.h[g]), int(b.w[g])
+        ref = O.jacobian(om, h, w, b.psf_of(g), b.truth[g])
+        got = jac[p * int(b.img_off[g]): p * int(b.img_off[g]) + p * h * w].reshape(p, h, w)
+        for k in range(p):
+            err = np.max(np.abs(got[k] - ref[k])) / np.max(np.abs(ref[k]))
+            assert err <= 1e-5, (g, k, err)
+
+
+def test_default_guess(cfg1, cfg2):
+    for b in (cfg1, cfg2):
+        om = from_spec(b.model)
+        gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+        p, mom = G.gm_default_guess(gm, _dev_batch(b))
+        p, mom = p.cpu().numpy(), mom.cpu().numpy()
+        for g in range(b.n):
+            rp, rm = O.default_guess(om, b.image(b.data, g), b.image(b.sigma, g))
+            assert np.allclose(p[g], rp, rtol=1e-6, atol=1e-9), (g, p[g], rp)
+            assert np.allclose(mom[g], rm, rtol=1e-6, atol=1e-9)
+
+
+def _fit_parity(b: S.Batch, min_pass: float):
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    names = S.MODEL_SPECS[b.model]["names"]
+    db = _dev_batch(b)
+    start, _ = G.gm_default_guess(gm, db)
+    start = start.cpu().numpy()
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, start)
+    both = (gs == 0) & (rs == 0)
+    assert np.mean(rs == 0) > 0.8
+    npass = 0
+    fails = []
+    for g in np.where(both)[0]:
+        sky_sig = float(np.median(b.image(b.sigma, g)))
+        ok, worst = param_parity(names, gp[g], rp[g], sky_sigma=sky_sig)
+        if ok.all():
+            npass += 1
+        else:
+            fails.append((int(g), float(worst.max())))
+    rate = npass / max(int(both.sum()), 1)
+    print(f"fit parity: {npass}/{int(both.sum())} pass; gpu converged {np.mean(gs == 0):.3f}, "
+          f"oracle converged {np.mean(rs == 0):.3f}; mean iters gpu {gn.mean():.1f} oracle {rn.mean():.1f}; "
+          f"fails {fails[:5]}", flush=True)
+    assert rate >= min_pass
+    return gp, rp, both
+
+
+def test_fit_sersic64(cfg1):
+    print("fit parity, sersic64 (64 galaxies)", flush=True)
+    _fit_parity(cfg1, 0.95)
+
+
+def test_fit_uneven(cfg2):
+    print("fit parity, uneven (12 galaxies)", flush=True)
+    _fit_parity(cfg2, 0.9)
+
+
+def test_param_errors(cfg1):
+    b = cfg1.subset(range(16))
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    at = b.truth
+    err, cov = G.gm_param_errors(gm, _dev_batch(b), at, want_cov=True)
+    err, cov = err.cpu().numpy(), cov.cpu().numpy()
+    for g in range(b.n):
+        re, rcov = O.param_errors(om, b.image(b.data, g), b.image(b.sigma, g), b.psf_of(g), at[g], want_cov=True)
+        assert np.allclose(err[g], re, rtol=1e-4, atol=0), (g, err[g], re)
+        assert np.allclose(cov[g], rcov, rtol=1e-4, atol=1e-4 * np.sqrt(np.outer(re, re)).max())
+
+
+def test_fit_is_deterministic(cfg1):
+    b = cfg1.subset(range(8))
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    db = _dev_batch(b)
+    start, _ = G.gm_default_guess(gm, db)
+    r1 = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    r2 = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    for a, c in zip(r1, r2):
+        assert np.array_equal(a, c)
+
+
+def test_masked_and_degenerate_galaxies(cfg1):
+    b = cfg1.subset(range(4))
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    om = from_spec(b.model)
+    omega = np.ones(b.npix, np.uint8)
+    omega[b.img_off[1]: b.img_off[1] + 64 * 64] = 0             # galaxy 1 fully masked
+    rng = np.random.default_rng(0)
+    o2 = b.img_off[2]
+    omega[o2: o2 + 64 * 64] = (rng.uniform(size=64 * 64) > 0.3).astype(np.uint8)   # 30% masked
+    db = _dev_batch(b, omega=omega)
+    start = b.truth.copy()
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    assert gs[1] == G.ST_STALLED and gc[1] == 0.0
+    rp, rc, rn, rs = O.fit(om, b.image(b.data, 2), b.image(b.sigma, 2), b.psf_of(2), start[2],
+                           omega=omega[o2: o2 + 64 * 64].reshape(64, 64))
+    assert rs == gs[2] == 0
+    ok, worst = param_parity(S.MODEL_SPECS["sersic"]["names"], gp[2], rp)
+    assert ok.all(), worst
+
+
+def test_fixed_parameters():
+    # n fixed at 4 (de Vaucouleurs) and sky fixed: a 6-column parameter vector
+    b = oracle_batch("sersic64", 6, seed=9)
+    spec_g = G.Model([G.Component(S.SERSIC, True, [0, 1, 2, 3, -1, 4, 5], [0, 0, 0, 0, 4.0, 0, 0]),
+                      G.Component(S.SKY, False, [-1], [1.0])], 6)
+    om = O.Model([O.Comp(O.SERSIC, True, [0, 1, 2, 3, -1, 4, 5], [0, 0, 0, 0, 4.0, 0, 0]),
+                  O.Comp(O.SKY, False, [-1], [1.0])], 6)
+    start = b.truth[:, [0, 1, 2, 3, 5, 6]]
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(spec_g, _dev_batch(b), start)]
+    for g in range(b.n):
+        rp, rc, rn, rs = O.fit(om, b.image(b.data, g), b.image(b.sigma, g), b.psf_of(g), start[g])
+        if rs != 0 or gs[g] != 0:
+            continue
+        ok, worst = param_parity(["x0", "y0", "mag", "re", "q", "pa"], gp[g], rp)
+        assert ok.all(), (g, worst)
+
+
+def test_abi_errors():
+    b = oracle_batch("sersic64", 2, seed=0)
+    gm = G.Model.from_spec(S.MODEL_SPECS["sersic"])
+    db = _dev_batch(b)
+    db.psf_k = np.array([14, 15], np.int32)          # even PSF side
+    with pytest.raises(G.GmError) as e:
+        G.gm_model_image(gm, db, b.truth)
+    assert e.value.code == G.GM_EINVAL
+    bad = G.Model([G.Component(S.KING, True, [0, 1, 2, 3, 4, 5, 6], [0] * 7 + [2.0])], 7)
+    with pytest.raises(G.GmError) as e:
+        G.gm_model_image(bad, _dev_batch(b), np.zeros((2, 7)))
+    assert e.value.code == G.GM_EUNSUPPORTED
+    empty = G.Batch(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0),
+                    np.zeros(0))
+    assert G.gm_model_image(gm, empty, np.zeros((0, 8))).numel() == 0

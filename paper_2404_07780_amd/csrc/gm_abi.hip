@@ -15,7 +15,6 @@
 #include <numeric>
 #include <vector>
 
-#include "gmfit.h"
 #include "gm_kernels.h"
 
 using namespace gm;
@@ -219,14 +218,23 @@ int max_k(const gm_batch *b)
     return k;
 }
 
-// Stage meta [+ extra bytes] into the device workspace; returns device pointers.
-int stage(gm_ctx *c, const gm_batch *b, const void *extra, size_t extra_bytes, hipStream_t st, Meta **dmeta,
-          void **dextra)
+// Device workspace of one call: [meta | extra | queue counter].
+struct Staged {
+    Meta *meta;
+    void *extra;
+    int *queue;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Stage meta [+ extra bytes] into the device workspace.
+int stage(gm_ctx *c, const gm_batch *b, const void *extra, size_t extra_bytes, hipStream_t st, Staged *out)
 {
-    size_t mb = sizeof(Meta) * (size_t)b->n_gal;
-    size_t mb_al = (mb + 255) & ~(size_t)255;
-    size_t total = mb_al + extra_bytes + 256;
-    int rc = ensure_host(c, total);
+    size_t mb_al = align256(sizeof(Meta) * (size_t)b->n_gal);
+    size_t ex_al = align256(extra_bytes);
+    size_t q_off = mb_al + ex_al;
+    size_t total = q_off + 256;
+    int rc = ensure_host(c, mb_al + ex_al);
     if (rc) return rc;
     rc = ensure_dev(c, total);
     if (rc) return rc;
@@ -241,20 +249,15 @@ int stage(gm_ctx *c, const gm_batch *b, const void *extra, size_t extra_bytes, h
     }
     char *hp = reinterpret_cast<char *>(c->ws.host);
     if (extra_bytes) memcpy(hp + mb_al, extra, extra_bytes);
-    if (hipMemcpyAsync(c->ws.dev, c->ws.host, mb_al + extra_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    if (hipMemcpyAsync(c->ws.dev, c->ws.host, mb_al + ex_al, hipMemcpyHostToDevice, st) != hipSuccess)
         return GM_EHIP;
     if (hipEventRecord(c->ws.staged, st) != hipSuccess) return GM_EHIP;
     c->ws.pending = true;
-    *dmeta = reinterpret_cast<Meta *>(c->ws.dev);
-    if (dextra) *dextra = reinterpret_cast<char *>(c->ws.dev) + mb_al;
+    char *dp = reinterpret_cast<char *>(c->ws.dev);
+    out->meta = reinterpret_cast<Meta *>(dp);
+    out->extra = dp + mb_al;
+    out->queue = reinterpret_cast<int *>(dp + q_off);
     return GM_OK;
-}
-
-// queue counter lives in the last 256 bytes of the staged region
-int *queue_ptr(gm_ctx *c, size_t staged_bytes)
-{
-    size_t off = (staged_bytes + 255) & ~(size_t)255;
-    return reinterpret_cast<int *>(reinterpret_cast<char *>(c->ws.dev) + off);
 }
 
 template <class F>
@@ -263,55 +266,98 @@ size_t static_lds()
     return sizeof(EvalShared<F>) + sizeof(LMShared<F>) + 64;
 }
 
-template <class F>
-int lds_for(int K, size_t *bytes)
+// Dynamic LDS of a kernel with NG plane groups for PSF side K: the plane
+// buffer, which also hosts the window partial sums, the wave partial sums of
+// the normal equations and the thread-0 solver temporaries.
+template <class F, int NG>
+size_t lds_bytes(int K)
 {
-    size_t dyn = planes_bytes<F>(K);
-    // the plane buffer also hosts the wave partial sums and solver temporaries
-    size_t need = std::max({dyn, (size_t)NWAVE * (1 + F::P + F::P * (F::P + 1) / 2) * 8,
-                            (size_t)3 * F::P * F::P * 8, (size_t)MAXWIN * 16 * F::NWV * 4});
-    if (need + static_lds<F>() > kMaxLds) return GM_EUNSUPPORTED;
-    *bytes = need;
+    return std::max({planes_bytes<F, NG>(K), (size_t)NWAVE * (1 + F::P + F::P * (F::P + 1) / 2) * 8,
+                     (size_t)3 * F::P * F::P * 8, window_scratch_bytes<F>()});
+}
+
+// Plane-group variants compiled per family (the first is the default).
+template <class F> struct Groups;
+template <> struct Groups<FamSersic> { static constexpr int a = 1, b = 2; };
+template <> struct Groups<FamBulgeDisk> { static constexpr int a = 2, b = 3; };
+
+// Fewest groups that let two workgroups share a CU, else fewest that fit.
+template <class F>
+int pick_groups(int K, int *ng, size_t *lds)
+{
+    constexpr int A = Groups<F>::a, B = Groups<F>::b;
+    size_t la = lds_bytes<F, A>(K) + static_lds<F>(), lb = lds_bytes<F, B>(K) + static_lds<F>();
+    if (2 * la <= kMaxLds) { *ng = A; *lds = lds_bytes<F, A>(K); return GM_OK; }
+    if (2 * lb <= kMaxLds) { *ng = B; *lds = lds_bytes<F, B>(K); return GM_OK; }
+    if (la <= kMaxLds) { *ng = A; *lds = lds_bytes<F, A>(K); return GM_OK; }
+    if (lb <= kMaxLds) { *ng = B; *lds = lds_bytes<F, B>(K); return GM_OK; }
+    return GM_EUNSUPPORTED;
+}
+
+template <typename Kern>
+int prepare(Kern kern, size_t lds, int *blocks_per_cu)
+{
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return GM_EHIP;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds) != hipSuccess) return GM_EHIP;
+    *blocks_per_cu = std::max(nb, 1);
     return GM_OK;
 }
 
-template <class F, int KT>
-int launch_fit_kt(const ModelArgs &ma, const BatchArgs &ba, const FitArgs &fa, int grid, size_t lds, hipStream_t st)
+template <class F, int KT, int NG>
+int launch_fit_k(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArgs &fa, size_t lds, hipStream_t st)
 {
-    auto kern = lm_fit_kernel<F, KT>;
-    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return GM_EHIP;
+    auto kern = lm_fit_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(fa.n_gal, per_cu * c->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, fa);
     return hip_fail(hipGetLastError());
 }
 
-template <class F, int KT>
-int launch_err_kt(const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, int grid, size_t lds, hipStream_t st)
+template <class F, int KT, int NG>
+int launch_err_k(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, hipStream_t st)
 {
-    auto kern = errors_kernel<F, KT>;
-    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return GM_EHIP;
+    auto kern = errors_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(ea.n_gal, per_cu * c->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, ea);
     return hip_fail(hipGetLastError());
 }
 
-template <class F, int KT>
-int launch_img_kt(const ModelArgs &ma, const BatchArgs &ba, const ImageArgs &ia, int grid, size_t lds, hipStream_t st)
+template <class F, int KT, int NG>
+int launch_img_k(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ImageArgs &ia, size_t lds, hipStream_t st)
 {
-    auto kern = image_kernel<F, KT>;
-    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return GM_EHIP;
+    auto kern = image_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(ia.n_tiles, 4 * per_cu * c->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, ia);
     return hip_fail(hipGetLastError());
 }
+
+// Dispatch on the compile-time PSF side and the plane-group count.
+#define GM_KT_NG_DISPATCH(LAUNCH, F, kt, ng, ...)                                              \
+    ((kt) == 15 ? ((ng) == Groups<F>::a ? LAUNCH<F, 15, Groups<F>::a>(__VA_ARGS__)             \
+                                        : LAUNCH<F, 15, Groups<F>::b>(__VA_ARGS__))            \
+     : (kt) == 25 ? ((ng) == Groups<F>::a ? LAUNCH<F, 25, Groups<F>::a>(__VA_ARGS__)           \
+                                          : LAUNCH<F, 25, Groups<F>::b>(__VA_ARGS__))          \
+                  : ((ng) == Groups<F>::a ? LAUNCH<F, 0, Groups<F>::a>(__VA_ARGS__)            \
+                                          : LAUNCH<F, 0, Groups<F>::b>(__VA_ARGS__)))
 
 // ---------------------------------------------------------------- per-call drivers
 template <class F>
 int run_fit(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, const gm_fit_opts *o, double *params, double *chi2,
             int32_t *niter, int32_t *status, hipStream_t st)
 {
+    int ng;
     size_t lds;
-    int rc = lds_for<F>(max_k(b), &lds);
+    int rc = pick_groups<F>(max_k(b), &ng, &lds);
     if (rc) return rc;
     // longest-processing-time order: biggest cutouts (times PSF area) first
     std::vector<int> order(b->n_gal);
@@ -319,20 +365,16 @@ int run_fit(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, const gm_fit_opts
     std::vector<double> cost(b->n_gal);
     for (int g = 0; g < b->n_gal; ++g) cost[g] = (double)b->h[g] * b->w[g] * b->psf_k[g] * b->psf_k[g];
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    Meta *dmeta;
-    void *dorder;
-    size_t ob = sizeof(int) * (size_t)b->n_gal;
-    rc = stage(c, b, order.data(), ob, st, &dmeta, &dorder);
+    Staged sg;
+    rc = stage(c, b, order.data(), sizeof(int) * (size_t)b->n_gal, st, &sg);
     if (rc) return rc;
-    size_t mb_al = ((sizeof(Meta) * (size_t)b->n_gal) + 255) & ~(size_t)255;
-    int *queue = queue_ptr(c, mb_al + ob);
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, queue, 0);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
-    BatchArgs ba{dmeta, b->data, b->sigma, b->psf, b->omega};
+    BatchArgs ba{sg.meta, b->data, b->sigma, b->psf, b->omega};
     FitArgs fa{};
-    fa.order = reinterpret_cast<const int *>(dorder);
+    fa.order = reinterpret_cast<const int *>(sg.extra);
     fa.n_gal = b->n_gal;
-    fa.queue = queue;
+    fa.queue = sg.queue;
     fa.params = params;
     fa.chi2 = chi2;
     fa.niter = niter;
@@ -340,67 +382,52 @@ int run_fit(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, const gm_fit_opts
     fa.max_iter = o ? o->max_iter : 100;
     fa.lambda0 = o ? o->lambda0 : 1e-3;
     fa.tol = o ? o->step_tol : 1e-4;
-    int per_cu = (int)(kMaxLds / (lds + static_lds<F>()));
-    int grid = std::min(b->n_gal, std::max(1, per_cu) * c->num_cu);
-    switch (batch_kt(b)) {
-    case 15: return launch_fit_kt<F, 15>(ma, ba, fa, grid, lds, st);
-    case 25: return launch_fit_kt<F, 25>(ma, ba, fa, grid, lds, st);
-    default: return launch_fit_kt<F, 0>(ma, ba, fa, grid, lds, st);
-    }
+    return GM_KT_NG_DISPATCH(launch_fit_k, F, batch_kt(b), ng, c, ma, ba, fa, lds, st);
 }
 
 template <class F>
 int run_errors(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, const double *params, double *err, double *cov,
                hipStream_t st)
 {
+    int ng;
     size_t lds;
-    int rc = lds_for<F>(max_k(b), &lds);
+    int rc = pick_groups<F>(max_k(b), &ng, &lds);
     if (rc) return rc;
-    Meta *dmeta;
-    rc = stage(c, b, nullptr, 0, st, &dmeta, nullptr);
+    Staged sg;
+    rc = stage(c, b, nullptr, 0, st, &sg);
     if (rc) return rc;
-    BatchArgs ba{dmeta, b->data, b->sigma, b->psf, b->omega};
+    BatchArgs ba{sg.meta, b->data, b->sigma, b->psf, b->omega};
     ErrArgs ea{params, err, cov, b->n_gal};
-    int grid = std::min(b->n_gal, 4 * c->num_cu);
-    switch (batch_kt(b)) {
-    case 15: return launch_err_kt<F, 15>(ma, ba, ea, grid, lds, st);
-    case 25: return launch_err_kt<F, 25>(ma, ba, ea, grid, lds, st);
-    default: return launch_err_kt<F, 0>(ma, ba, ea, grid, lds, st);
-    }
+    return GM_KT_NG_DISPATCH(launch_err_k, F, batch_kt(b), ng, c, ma, ba, ea, lds, st);
 }
 
 template <class F>
 int run_image(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, const double *params, float *out, int mode,
               hipStream_t st)
 {
+    int ng;
     size_t lds;
-    int rc = lds_for<F>(max_k(b), &lds);
+    int rc = pick_groups<F>(max_k(b), &ng, &lds);
     if (rc) return rc;
     std::vector<TileItem> tiles;
     for (int g = 0; g < b->n_gal; ++g)
         for (int ty = 0; ty < (b->h[g] + TILE - 1) / TILE; ++ty)
             for (int tx = 0; tx < (b->w[g] + TILE - 1) / TILE; ++tx) tiles.push_back({g, ty, tx, 0});
-    Meta *dmeta;
-    void *dtiles;
-    rc = stage(c, b, tiles.data(), sizeof(TileItem) * tiles.size(), st, &dmeta, &dtiles);
+    Staged sg;
+    rc = stage(c, b, tiles.data(), sizeof(TileItem) * tiles.size(), st, &sg);
     if (rc) return rc;
-    BatchArgs ba{dmeta, b->data, b->sigma, b->psf, b->omega};
-    ImageArgs ia{reinterpret_cast<const TileItem *>(dtiles), (int)tiles.size(), params, out, mode};
-    int grid = std::min((int)tiles.size(), 8 * c->num_cu);
-    switch (batch_kt(b)) {
-    case 15: return launch_img_kt<F, 15>(ma, ba, ia, grid, lds, st);
-    case 25: return launch_img_kt<F, 25>(ma, ba, ia, grid, lds, st);
-    default: return launch_img_kt<F, 0>(ma, ba, ia, grid, lds, st);
-    }
+    BatchArgs ba{sg.meta, b->data, b->sigma, b->psf, b->omega};
+    ImageArgs ia{reinterpret_cast<const TileItem *>(sg.extra), (int)tiles.size(), params, out, mode};
+    return GM_KT_NG_DISPATCH(launch_img_k, F, batch_kt(b), ng, c, ma, ba, ia, lds, st);
 }
 
 template <class F>
 int run_guess(gm_ctx *c, const ModelArgs &ma, const gm_batch *b, double *params, double *moments, hipStream_t st)
 {
-    Meta *dmeta;
-    int rc = stage(c, b, nullptr, 0, st, &dmeta, nullptr);
+    Staged sg;
+    int rc = stage(c, b, nullptr, 0, st, &sg);
     if (rc) return rc;
-    BatchArgs ba{dmeta, b->data, b->sigma, b->psf, b->omega};
+    BatchArgs ba{sg.meta, b->data, b->sigma, b->psf, b->omega};
     GuessArgs ga{params, moments, b->n_gal};
     int grid = std::min(b->n_gal, 8 * c->num_cu);
     hipLaunchKernelGGL(guess_kernel<F>, dim3(grid), dim3(NT), 0, st, ma, ba, ga);

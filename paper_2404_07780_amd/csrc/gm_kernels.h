@@ -1,25 +1,31 @@
-// gm_kernels.hip -- gfx950 kernels of libgmfit.
+// gm_kernels.h -- gfx950 kernels of libgmfit.
 //
 // Work decomposition.  A galaxy's cutout is processed in 32 x 32 output tiles
-// by one 256-thread workgroup.  For a tile, the profile value and the
-// derivative of the light with respect to every LM variable are evaluated
-// (FP32) on the tile's (32 + K - 1)^2 input region straight into LDS, one
-// plane per quantity; the oversampled central window is evaluated once per
-// model evaluation into a small LDS table.  Each thread then convolves a 1 x 4
-// strip of outputs of every plane with the PSF (true convolution, zero
-// padding), streaming a (K + 3)-float row segment from LDS per PSF row and
-// reading the PSF through the scalar cache, and keeps the 4 x planes results
-// in registers.  The fitting kernel turns them into residuals and FP64
-// normal-equation sums without writing any image to memory.
+// by one 256-thread workgroup.  For a tile, the light (FP64) and its FP32
+// derivatives with respect to every LM variable are evaluated on the tile's
+// (32 + K - 1)^2 input region straight into LDS, one plane per quantity; the
+// oversampled central window is evaluated once per model evaluation into a
+// small LDS table.  Each thread then convolves a 1 x 4 strip of outputs of
+// every plane with the PSF (true convolution, zero padding), streaming one
+// row segment from LDS per PSF row and reading the PSF through the scalar
+// cache; the results stay in registers.  When the planes of a model do not fit
+// LDS together (or fit only one workgroup per CU) they are processed in NG
+// groups, re-evaluating the profile per group (only the first group needs the
+// FP64 light).  The fitting kernel turns the convolved planes into residuals
+// and FP64 normal-equation sums without writing any image to memory.
 //
 // gm_fit_batch runs one persistent kernel: each workgroup pulls galaxies, in
 // descending-cost order, from an atomic queue and runs the whole
 // Levenberg-Marquardt iteration for a galaxy; thread 0 does the FP64 damped
 // Cholesky solve and accept/reject between evaluations.
+#pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "gmfit.h"
 #include "gm_device.h"
 
 namespace gm {
@@ -29,6 +35,7 @@ constexpr int NT = 256;
 constexpr int NWAVE = NT / 64;
 constexpr int MAXP = 16;
 constexpr int MAXWIN = 25;      // oversampled window of at most 5 x 5 pixels
+constexpr int MAXOSF = 16;      // sub-samples per pixel side
 
 struct Meta {
     int32_t h, w, k, pad;
@@ -53,34 +60,72 @@ struct BatchArgs {
 
 __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Input-region geometry of a tile for PSF side K.
-__host__ __device__ inline int seg_vec4(int K) { return (K + 3 + 3) / 4; }
+// Input-region geometry of a tile for PSF side K (row pitch IWP in elements).
 __host__ __device__ inline int region_h(int K) { return TILE + K - 1; }
-__host__ __device__ inline int region_wp(int K) { return 28 + 4 * seg_vec4(K); }
+__host__ __device__ inline int region_wp(int K) { return 28 + 4 * ((K + 3 + 3) / 4); }
 
-template <class F>
+// Plane groups: plane 0 (FP64) counts two units, the others one; groups are
+// contiguous and balanced in units.
+__host__ __device__ constexpr int group_bound(int npl, int ng, int g)
+{
+    if (g <= 0) return 0;
+    if (g >= ng) return npl;
+    int target = ((npl + 1) * g + ng - 1) / ng, acc = 0;
+    for (int q = 0; q < npl; ++q) {
+        acc += (q == 0 ? 2 : 1);
+        if (acc >= target) return q + 1;
+    }
+    return npl;
+}
+__host__ __device__ constexpr int group_units(int npl, int ng, int g)
+{
+    int lo = group_bound(npl, ng, g), hi = group_bound(npl, ng, g + 1);
+    return hi - lo + (lo == 0 ? 1 : 0);
+}
+__host__ __device__ constexpr int max_group_units(int npl, int ng)
+{
+    int m = 0;
+    for (int g = 0; g < ng; ++g) m = group_units(npl, ng, g) > m ? group_units(npl, ng, g) : m;
+    return m;
+}
+
+template <class F, int NG>
 __host__ __device__ inline size_t planes_bytes(int K)
 {
-    return (size_t)F::NPL * region_h(K) * region_wp(K) * sizeof(float);
+    return (size_t)max_group_units(F::NPL, NG) * region_h(K) * region_wp(K) * sizeof(float);
 }
 
 // ---------------------------------------------------------------- per-evaluation state in LDS
 template <class F>
 struct EvalShared {
     typename F::Prep prep;
-    float win[F::NCOMP][MAXWIN][F::NWV];
+    double win0[F::NCOMP][MAXWIN];
+    float win[F::NCOMP][MAXWIN][F::ND];
 };
 
-// Scalar prologue + oversampled window tables.  u: LDS (FP64, internal).
-// scratch: LDS float area of at least MAXWIN * osf * NWV floats.
+// scratch needed by the window tables (in the plane buffer)
+template <class F>
+__host__ __device__ constexpr size_t window_scratch_bytes()
+{
+    return (size_t)MAXWIN * MAXOSF * (sizeof(double) + F::ND * sizeof(float));
+}
+
+// Scalar prologue (wave 0) + oversampled window tables (all threads).
+// u: LDS (FP64, internal).  scratch: the idle plane buffer.
 template <class F>
 __device__ void eval_prologue(const double *u, const ModelArgs &ma, int H, int W, EvalShared<F> &sh, float *scratch)
 {
     const int tid = threadIdx.x;
-    if (tid == 0) F::prep(u, ma.m0, H, W, ma.osf, ma.osw, sh.prep);
+    if (tid < 64) {
+        typename F::Prep lp;
+        F::prep(u, ma.m0, H, W, ma.osf, ma.osw, tid, lp);
+        if (tid == 0) sh.prep = lp;
+    }
     __syncthreads();
     const int f = ma.osf;
-    const float invf = 1.0f / (float)f;
+    const double invf = 1.0 / (double)f;
+    double *sd = reinterpret_cast<double *>(scratch);
+    float *sf = scratch + 2 * MAXWIN * MAXOSF;
 #pragma unroll 1
     for (int c = 0; c < F::NCOMP; ++c) {
         const Geo &g = F::geo(sh.prep, c);
@@ -91,147 +136,235 @@ __device__ void eval_prologue(const double *u, const ModelArgs &ma, int H, int W
         for (int it = tid; it < items; it += NT) {
             int pix = it / f, t = it - pix * f;
             int i = g.wi0 + pix / ww, j = g.wj0 + pix % ww;
-            float acc[F::NWV];
+            double aI = 0.0;
+            float ad[F::ND];
 #pragma unroll
-            for (int q = 0; q < F::NWV; ++q) acc[q] = 0.0f;
-            float ys = ((float)t + 0.5f) * invf;
+            for (int q = 0; q < F::ND; ++q) ad[q] = 0.0f;
+            const double dy = ((double)(H - i) - ((double)t + 0.5) * invf) - g.y0;
             for (int s = 0; s < f; ++s) {
-                float xs = ((float)s + 0.5f) * invf, dx, dy, v[F::NWV];
-                offsets(g, (float)j, xs, (float)(H - i), ys, dx, dy);
-                F::comp_pt(sh.prep, c, dx, dy, v);
+                const double dx = ((double)j + ((double)s + 0.5) * invf) - g.x0;
+                double I;
+                float d[F::ND];
+                F::template comp_pt<true>(sh.prep, c, dx, dy, I, d);
+                aI += I;
 #pragma unroll
-                for (int q = 0; q < F::NWV; ++q) acc[q] += v[q];
+                for (int q = 0; q < F::ND; ++q) ad[q] += d[q];
             }
+            sd[it] = aI;
 #pragma unroll
-            for (int q = 0; q < F::NWV; ++q) scratch[it * F::NWV + q] = acc[q];
+            for (int q = 0; q < F::ND; ++q) sf[it * F::ND + q] = ad[q];
         }
         __syncthreads();
-        const float norm = 1.0f / (float)(f * f);
+        const double norm = 1.0 / (double)(f * f);
         for (int pix = tid; pix < nwin; pix += NT) {
+            double s0 = 0.0;
+            for (int t = 0; t < f; ++t) s0 += sd[pix * f + t];
+            sh.win0[c][pix] = s0 * norm;
 #pragma unroll
-            for (int q = 0; q < F::NWV; ++q) {
+            for (int q = 0; q < F::ND; ++q) {
                 float s = 0.0f;
-                for (int t = 0; t < f; ++t) s += scratch[(pix * f + t) * F::NWV + q];
-                sh.win[c][pix][q] = s * norm;
+                for (int t = 0; t < f; ++t) s += sf[(pix * f + t) * F::ND + q];
+                sh.win[c][pix][q] = s * (float)norm;
             }
         }
         __syncthreads();
     }
 }
 
-// Plane vector (light + derivatives) of the convolved components at pixel (i, j).
-template <class F>
-__device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, float *pl)
+// Light (FP64 if F64) and derivative planes (dp[q - 1] for plane q) of the
+// convolved components at pixel (i, j).
+template <class F, bool F64>
+__device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, double &v0, float *dp)
 {
+    v0 = 0.0;
 #pragma unroll
-    for (int q = 0; q < F::NPL; ++q) pl[q] = 0.0f;
+    for (int q = 0; q < F::NPL - 1; ++q) dp[q] = 0.0f;
 #pragma unroll
     for (int c = 0; c < F::NCOMP; ++c) {
         const Geo &g = F::geo(sh.prep, c);
-        float v[F::NWV];
+        double I;
+        float d[F::ND];
         if (i >= g.wi0 && i <= g.wi1 && j >= g.wj0 && j <= g.wj1) {
-            const float *t = sh.win[c][(i - g.wi0) * (g.wj1 - g.wj0 + 1) + (j - g.wj0)];
+            const int pix = (i - g.wi0) * (g.wj1 - g.wj0 + 1) + (j - g.wj0);
+            I = sh.win0[c][pix];
 #pragma unroll
-            for (int q = 0; q < F::NWV; ++q) v[q] = t[q];
+            for (int q = 0; q < F::ND; ++q) d[q] = sh.win[c][pix][q];
         } else {
-            float dx, dy;
-            offsets(g, (float)j, 0.5f, (float)(H - i), 0.5f, dx, dy);
-            F::comp_pt(sh.prep, c, dx, dy, v);
+            const double dx = ((double)j + 0.5) - g.x0;
+            const double dy = ((double)(H - i) - 0.5) - g.y0;
+            F::template comp_pt<F64>(sh.prep, c, dx, dy, I, d);
         }
-        F::scatter(c, v, pl);
+        v0 += I;
+        F::scatter(c, d, dp);
     }
 }
 
-// Fill the LDS planes of the input region of the tile at (ti0, tj0).
-template <class F>
-__device__ void fill_region(const EvalShared<F> &sh, float *planes, int H, int W, int K, int ti0, int tj0)
+// Fill the LDS planes LO..HI-1 of the input region of the tile at (ti0, tj0).
+// Layout: if LO == 0 the FP64 light plane comes first (two float units),
+// then the FP32 planes in order.
+template <class F, int LO, int HI>
+__device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, int K, int ti0, int tj0)
 {
     const int IH = region_h(K), IWP = region_wp(K), IW = TILE + K - 1, c = (K - 1) / 2;
     const int plane_sz = IH * IWP;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *b0 = reinterpret_cast<double *>(buf);
+    float *bf = (LO == 0) ? buf + 2 * plane_sz : buf;
+    constexpr int QLO = LO == 0 ? 1 : LO;
     for (int ri = wave; ri < IH; ri += NWAVE) {
         const int i = ti0 - c + ri;
         for (int ci = lane; ci < IWP; ci += 64) {
             const int j = tj0 - c + ci;
-            float pl[F::NPL];
+            double v0 = 0.0;
+            float dp[F::NPL - 1];
             if (ci < IW && i >= 0 && i < H && j >= 0 && j < W) {
-                planes_at<F>(sh, i, j, H, pl);
+                planes_at<F, LO == 0>(sh, i, j, H, v0, dp);
             } else {
 #pragma unroll
-                for (int q = 0; q < F::NPL; ++q) pl[q] = 0.0f;
+                for (int q = 0; q < F::NPL - 1; ++q) dp[q] = 0.0f;
             }
-            float *dst = planes + ri * IWP + ci;
+            const int idx = ri * IWP + ci;
+            if constexpr (LO == 0) b0[idx] = v0;
 #pragma unroll
-            for (int q = 0; q < F::NPL; ++q) dst[q * plane_sz] = pl[q];
+            for (int q = QLO; q < HI; ++q) bf[(q - QLO) * plane_sz + idx] = dp[q - 1];
         }
     }
 }
 
-// Convolve every plane for this thread's 1 x 4 output strip (tile row r,
-// columns 4 cg .. 4 cg + 3).  KT > 0: compile-time PSF side; KT == 0: any K.
-template <class F, int KT>
-__device__ inline void conv_strip(const float *__restrict__ planes, int K, const float *__restrict__ psf, int r,
-                                  int cg, float (&acc)[F::NPL][4])
+// The PSF is read through the constant address space with a wave-uniform
+// offset: such loads are scalar (s_load through the scalar cache) and the taps
+// reach the FMAs as SGPR operands.
+typedef __attribute__((address_space(4))) const float cfloat;
+
+__device__ inline int64_t uniform64(int64_t x)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One PSF row (KT taps) against a row segment: acc[t] += sum_v p[v] seg[t + KT-1-v].
+template <int KT, typename T>
+__device__ inline void row_fma(const T *seg, const cfloat *pr, T &a0, T &a1, T &a2, T &a3)
+{
+#pragma unroll
+    for (int v = 0; v < KT; ++v) {
+        const T pv = (T)pr[v];
+        a0 = fma(pv, seg[KT - 1 - v], a0);
+        a1 = fma(pv, seg[KT - v], a1);
+        a2 = fma(pv, seg[KT + 1 - v], a2);
+        a3 = fma(pv, seg[KT + 2 - v], a3);
+    }
+}
+
+// Load the (KT + 3)-element row segment at p (16-byte aligned) into seg.
+template <int KT, typename T>
+__device__ inline void load_seg(const T *p, T *seg)
+{
+    constexpr int PER = 16 / sizeof(T);
+    constexpr int NV = (KT + 3 + PER - 1) / PER;
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const V *rp = reinterpret_cast<const V *>(p);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        V t = rp[q];
+        if constexpr (sizeof(T) == 4) {
+            seg[4 * q] = t.x; seg[4 * q + 1] = t.y; seg[4 * q + 2] = t.z; seg[4 * q + 3] = t.w;
+        } else {
+            seg[2 * q] = t.x; seg[2 * q + 1] = t.y;
+        }
+    }
+}
+
+// Convolve one plane (elements of type T, row pitch IWP) for a 1 x 4 output
+// strip with a compile-time PSF side.  FP32 planes load the segment of the
+// next PSF row while the current one is used; the FP64 plane, whose segment
+// is twice as large, loads one row at a time.
+template <int KT, typename T>
+__device__ inline void conv_plane(const T *base, int r, int IWP, const cfloat *psf, T (&out)[4])
+{
+    constexpr int PER = 16 / sizeof(T);
+    constexpr int SEG = ((KT + 3 + PER - 1) / PER) * PER;
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if constexpr (sizeof(T) == 4) {
+        T sa[SEG], sb[SEG];
+        load_seg<KT>(base + (r + KT - 1) * IWP, sa);
+#pragma unroll 1
+        for (int u = 0; u + 1 < KT; u += 2) {
+            load_seg<KT>(base + (r + KT - 2 - u) * IWP, sb);
+            row_fma<KT>(sa, psf + u * KT, a0, a1, a2, a3);
+            if (u + 2 < KT) load_seg<KT>(base + (r + KT - 3 - u) * IWP, sa);
+            row_fma<KT>(sb, psf + (u + 1) * KT, a0, a1, a2, a3);
+        }
+        if (KT & 1) row_fma<KT>(sa, psf + (KT - 1) * KT, a0, a1, a2, a3);
+    } else {
+        T sa[SEG];
+#pragma unroll 1
+        for (int u = 0; u < KT; ++u) {
+            load_seg<KT>(base + (r + KT - 1 - u) * IWP, sa);
+            row_fma<KT>(sa, psf + u * KT, a0, a1, a2, a3);
+        }
+    }
+    out[0] = a0; out[1] = a1; out[2] = a2; out[3] = a3;
+}
+
+// Any PSF side (slow path): taps read one by one from LDS.
+template <typename T>
+__device__ inline void conv_plane_any(const T *base, int r, int K, int IWP, const cfloat *psf, T (&out)[4])
+{
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int u = 0; u < K; ++u) {
+        const T *rp = base + (r + K - 1 - u) * IWP;
+        const cfloat *pr = psf + u * K;
+        for (int v = 0; v < K; ++v) {
+            const T pv = (T)pr[v];
+            const T *sp = rp + K - 1 - v;
+            a0 = fma(pv, sp[0], a0);
+            a1 = fma(pv, sp[1], a1);
+            a2 = fma(pv, sp[2], a2);
+            a3 = fma(pv, sp[3], a3);
+        }
+    }
+    out[0] = a0; out[1] = a1; out[2] = a2; out[3] = a3;
+}
+
+// Convolve planes LO..HI-1 for this thread's 1 x 4 output strip (tile row r,
+// columns 4 cg .. 4 cg + 3): plane 0 in FP64, the derivative planes in FP32.
+// KT > 0: compile-time PSF side; 0: any K.
+template <class F, int KT, int LO, int HI>
+__device__ inline void conv_group(const float *__restrict__ buf, int K, const cfloat *psf, int r, int cg,
+                                  double (&acc0)[4], float (&acc)[F::NPL][4])
 {
     const int IH = region_h(K), IWP = region_wp(K);
     const int plane_sz = IH * IWP;
-    if constexpr (KT > 0) {
-        constexpr int NV4 = (KT + 3 + 3) / 4;
+    constexpr int QLO = LO == 0 ? 1 : LO;
+    const float *bf = (LO == 0) ? buf + 2 * plane_sz : buf;
+    if constexpr (LO == 0) {
+        const double *base = reinterpret_cast<const double *>(buf) + 4 * cg;
+        if constexpr (KT > 0) conv_plane<KT, double>(base, r, IWP, psf, acc0);
+        else conv_plane_any<double>(base, r, K, IWP, psf, acc0);
+    }
 #pragma unroll
-        for (int pl = 0; pl < F::NPL; ++pl) {
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            const float *base = planes + pl * plane_sz + 4 * cg;
-#pragma unroll 1
-            for (int u = 0; u < KT; ++u) {
-                const float4 *rp = reinterpret_cast<const float4 *>(base + (r + KT - 1 - u) * IWP);
-                float seg[NV4 * 4];
-#pragma unroll
-                for (int q = 0; q < NV4; ++q) {
-                    float4 t4 = rp[q];
-                    seg[4 * q] = t4.x;
-                    seg[4 * q + 1] = t4.y;
-                    seg[4 * q + 2] = t4.z;
-                    seg[4 * q + 3] = t4.w;
-                }
-                const float *pr = psf + u * KT;
-#pragma unroll
-                for (int v = 0; v < KT; ++v) {
-                    const float pv = pr[v];
-                    a0 = fmaf(pv, seg[KT - 1 - v], a0);
-                    a1 = fmaf(pv, seg[KT - v], a1);
-                    a2 = fmaf(pv, seg[KT + 1 - v], a2);
-                    a3 = fmaf(pv, seg[KT + 2 - v], a3);
-                }
-            }
-            acc[pl][0] = a0; acc[pl][1] = a1; acc[pl][2] = a2; acc[pl][3] = a3;
-        }
-    } else {
-#pragma unroll
-        for (int pl = 0; pl < F::NPL; ++pl) {
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            const float *base = planes + pl * plane_sz + 4 * cg;
-            for (int u = 0; u < K; ++u) {
-                const float *rp = base + (r + K - 1 - u) * IWP;
-                const float *pr = psf + u * K;
-                for (int v = 0; v < K; ++v) {
-                    const float pv = pr[v];
-                    const float *sp = rp + K - 1 - v;
-                    a0 = fmaf(pv, sp[0], a0);
-                    a1 = fmaf(pv, sp[1], a1);
-                    a2 = fmaf(pv, sp[2], a2);
-                    a3 = fmaf(pv, sp[3], a3);
-                }
-            }
-            acc[pl][0] = a0; acc[pl][1] = a1; acc[pl][2] = a2; acc[pl][3] = a3;
-        }
+    for (int pl = QLO; pl < HI; ++pl) {
+        const float *base = bf + (pl - QLO) * plane_sz + 4 * cg;
+        if constexpr (KT > 0) conv_plane<KT, float>(base, r, IWP, psf, acc[pl]);
+        else conv_plane_any<float>(base, r, K, IWP, psf, acc[pl]);
     }
 }
 
-__device__ inline double wave_sum(double v)
+// All groups of one tile: fill, convolve, leave the buffer idle.
+template <class F, int KT, int NG, int G = 0>
+__device__ inline void tile_planes(const EvalShared<F> &sh, float *buf, int H, int W, int K, int ti0, int tj0,
+                                   const cfloat *psf, int r, int cg, double (&acc0)[4], float (&acc)[F::NPL][4])
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    if constexpr (G < NG) {
+        constexpr int LO = group_bound(F::NPL, NG, G), HI = group_bound(F::NPL, NG, G + 1);
+        fill_region<F, LO, HI>(sh, buf, H, W, K, ti0, tj0);
+        __syncthreads();
+        conv_group<F, KT, LO, HI>(buf, K, psf, r, cg, acc0, acc);
+        __syncthreads();
+        tile_planes<F, KT, NG, G + 1>(sh, buf, H, W, K, ti0, tj0, psf, r, cg, acc0, acc);
+    }
 }
 
 __device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
@@ -242,10 +375,10 @@ __device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
     return ok ? 1.0f / (s * s) : 0.0f;
 }
 
-// One model evaluation at u (LDS): chi^2, g = J^T W r and the lower triangle
-// of A = J^T W J (internal LM variables), written to out_chi2/out_g/out_A
-// (LDS, A full p x p).  All threads of the workgroup call it.
-template <class F, int KT>
+// One model evaluation at u (LDS): chi^2, g = J^T W r and A = J^T W J
+// (internal LM variables), written to out_chi2/out_g/out_A (LDS, A full
+// P x P).  All threads of the workgroup call it.
+template <class F, int KT, int NG>
 __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &ba, const Meta &me, EvalShared<F> &sh,
                          float *planes, double *out_chi2, double *out_g, double *out_A)
 {
@@ -254,21 +387,22 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     const int H = me.h, W = me.w, K = me.k;
     const int tid = threadIdx.x;
     eval_prologue<F>(u, ma, H, W, sh, planes);
-    const float sky = sh.prep.sky;
-    const float *psf = ba.psf + me.psf_off;
-    double red[NR];
+    const double sky = sh.prep.sky;
+    const cfloat *psf = (const cfloat *)(ba.psf + uniform64(me.psf_off));
+    // Per-thread partial sums: chi^2 in FP64 (it decides accept/reject), g and
+    // A in FP32 (a thread sums at most a few hundred pixels of them).
+    double c2 = 0.0;
+    float red[NR - 1];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) red[q] = 0.0;
+    for (int q = 0; q < NR - 1; ++q) red[q] = 0.0f;
     const int r = tid >> 3, cg = tid & 7;
     const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
     for (int ty = 0; ty < nty; ++ty) {
         for (int tx = 0; tx < ntx; ++tx) {
             const int ti0 = ty * TILE, tj0 = tx * TILE;
-            fill_region<F>(sh, planes, H, W, K, ti0, tj0);
-            __syncthreads();
+            double acc0[4];
             float acc[F::NPL][4];
-            conv_strip<F, KT>(planes, K, psf, r, cg, acc);
-            __syncthreads();
+            tile_planes<F, KT, NG>(sh, planes, H, W, K, ti0, tj0, psf, r, cg, acc0, acc);
             const int i = ti0 + r;
             if (i < H) {
 #pragma unroll
@@ -279,32 +413,35 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
                     float d;
                     const float wgt = pixel_weight(ba, idx, d);
                     if (wgt == 0.0f) continue;
-                    const double res = (double)(d - (acc[0][t] + sky));
-                    double J[P];
-#pragma unroll
-                    for (int k = 0; k < P; ++k) J[k] = (k == F::SKY) ? 1.0 : (double)acc[1 + k][t];
-                    const double wr = (double)wgt * res;
-                    red[0] = fma(wr, res, red[0]);
-#pragma unroll
-                    for (int k = 0; k < P; ++k) red[1 + k] = fma(wr, J[k], red[1 + k]);
+                    const double res = (double)d - (acc0[t] + sky);
+                    c2 = fma((double)wgt * res, res, c2);
+                    const float wr = wgt * (float)res;
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
-                        const double wj = (double)wgt * J[k];
+                        const float Jk = (k == F::SKY) ? 1.0f : acc[1 + k][t];
+                        red[k] = fmaf(wr, Jk, red[k]);
+                        const float wj = wgt * Jk;
 #pragma unroll
-                        for (int l = 0; l <= k; ++l)
-                            red[1 + P + k * (k + 1) / 2 + l] = fma(wj, J[l], red[1 + P + k * (k + 1) / 2 + l]);
+                        for (int l = 0; l <= k; ++l) {
+                            const float Jl = (l == F::SKY) ? 1.0f : acc[1 + l][t];
+                            red[P + k * (k + 1) / 2 + l] = fmaf(wj, Jl, red[P + k * (k + 1) / 2 + l]);
+                        }
                     }
                 }
             }
         }
     }
-    // fixed-order reduction: within each wave, then the waves in order
-    // (the planes are idle after the last tile's barrier: reuse them)
+    // fixed-order reduction in FP64: within each wave, then the waves in order
+    // (the plane buffer is idle after the last tile's barrier: reuse it)
     double *sred = reinterpret_cast<double *>(planes);
     const int lane = tid & 63, wave = tid >> 6;
+    {
+        double v = wave_sum(c2);
+        if (lane == 0) sred[wave * NR] = v;
+    }
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        double v = wave_sum(red[q]);
+    for (int q = 1; q < NR; ++q) {
+        double v = wave_sum((double)red[q - 1]);
         if (lane == 0) sred[wave * NR + q] = v;
     }
     __syncthreads();
@@ -564,7 +701,7 @@ __device__ void load_u(LMShared<F> &s, const ModelArgs &ma, const double *params
     }
 }
 
-template <class F, int KT>
+template <class F, int KT, int NG>
 __global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, FitArgs fa)
 {
     extern __shared__ float4 dyn_lds[];
@@ -586,31 +723,33 @@ __global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, 
             s.inv = tmp + 2 * F::P * F::P;
             load_u<F>(s, ma, fa.params + (int64_t)g * ma.p);
             clamp_u<F>(s.u, me.h, me.w);
-            s.t = 0;
+            for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
+            s.t = -1;             // -1: the next evaluation is the start point
             s.status = GM_ST_MAXITER;
             s.lambda = fa.lambda0;
             s.fresh = 1;
             s.action = ACT_EVAL;
         }
         __syncthreads();
-        evaluate<F, KT>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
-        if (tid == 0) {
-            project_fixed<F::P>(s.freev, s.A, s.g);
-            if (!isfinite(s.chi2)) {
-                s.status = GM_ST_NONFINITE;
-                s.action = ACT_DONE;
-            } else {
-                s.action = ACT_EVAL;
-            }
-        }
-        __syncthreads();
+        // one evaluation site: the start point first, then one trial per pass
         while (s.action != ACT_DONE) {
-            if (tid == 0) lm_propose<F>(s, fa, me.h, me.w);
-            __syncthreads();
-            const int act = s.action;
-            if (act == ACT_EVAL) {
-                evaluate<F, KT>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
-                if (tid == 0) lm_accept<F>(s);
+            if (s.action == ACT_EVAL)
+                evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
+            if (tid == 0) {
+                if (s.t < 0) {
+                    project_fixed<F::P>(s.freev, s.At, s.gt);
+                    for (int k = 0; k < F::P; ++k) s.g[k] = s.gt[k];
+                    for (int k = 0; k < F::P * F::P; ++k) s.A[k] = s.At[k];
+                    s.chi2 = s.chi2t;
+                    s.t = 0;
+                    if (!isfinite(s.chi2)) {
+                        s.status = GM_ST_NONFINITE;
+                        s.action = ACT_DONE;
+                    }
+                } else if (s.action == ACT_EVAL) {
+                    lm_accept<F>(s);
+                }
+                if (s.action != ACT_DONE) lm_propose<F>(s, fa, me.h, me.w);
             }
             __syncthreads();
         }
@@ -635,7 +774,7 @@ struct ErrArgs {
     int n_gal;
 };
 
-template <class F, int KT>
+template <class F, int KT, int NG>
 __global__ __launch_bounds__(NT) void errors_kernel(ModelArgs ma, BatchArgs ba, ErrArgs ea)
 {
     extern __shared__ float4 dyn_lds[];
@@ -648,7 +787,7 @@ __global__ __launch_bounds__(NT) void errors_kernel(ModelArgs ma, BatchArgs ba, 
         const Meta me = ba.meta[g];
         if (tid == 0) load_u<F>(s, ma, ea.params + (int64_t)g * ma.p);
         __syncthreads();
-        evaluate<F, KT>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
+        evaluate<F, KT, NG>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
         if (tid == 0) {
             double *tmp = reinterpret_cast<double *>(planes);
             s.L = tmp;
@@ -694,7 +833,7 @@ struct ImageArgs {
     int mode;
 };
 
-template <class F, int KT>
+template <class F, int KT, int NG>
 __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, ImageArgs ia)
 {
     extern __shared__ float4 dyn_lds[];
@@ -720,11 +859,11 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
         __syncthreads();
         eval_prologue<F>(su, ma, H, W, esh, planes);
         const int ti0 = ti.ty * TILE, tj0 = ti.tx * TILE;
-        fill_region<F>(esh, planes, H, W, K, ti0, tj0);
-        __syncthreads();
         const int r = tid >> 3, cg = tid & 7;
+        double acc0[4];
         float acc[F::NPL][4];
-        conv_strip<F, KT>(planes, K, ba.psf + me.psf_off, r, cg, acc);
+        tile_planes<F, KT, NG>(esh, planes, H, W, K, ti0, tj0, (const cfloat *)(ba.psf + uniform64(me.psf_off)), r,
+                               cg, acc0, acc);
         const int i = ti0 + r;
         if (i < H) {
 #pragma unroll
@@ -733,7 +872,7 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
                 if (j >= W) continue;
                 const int64_t pix = (int64_t)i * W + j;
                 if (ia.mode == 0) {
-                    ia.out[me.img_off + pix] = acc[0][t] + esh.prep.sky;
+                    ia.out[me.img_off + pix] = (float)(acc0[t] + esh.prep.sky);
                 } else {
                     float *jo = ia.out + (int64_t)ma.p * me.img_off;
 #pragma unroll
@@ -770,7 +909,7 @@ __device__ inline double block_sum(double v, double *sred)
 
 // Moments: sky0 = mean of usable pixels in the 2-px frame; S = usable pixels
 // with D - sky0 > 3 sigma; flux, flux-weighted centroid and central second
-// moments over S.  Start vector per family (see host documentation).
+// moments over S.  Start vector per family (F::default_guess).
 template <class F>
 __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, GuessArgs ga)
 {
@@ -807,8 +946,7 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
         fx = block_sum(fx, sred);
         fy = block_sum(fy, sred);
         cnt = block_sum(cnt, sred);
-        // block max of the peak
-        {
+        {   // block max of the peak
             const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) pk = fmax(pk, __shfl_xor(pk, o, 64));

@@ -36,6 +36,21 @@ from paper_2404_07780_amd import gmfit as G  # noqa: E402
 from paper_2404_07780_amd import synth as S  # noqa: E402
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+
+# HBM bytes per lm_fit launch on the default workload (8192 galaxies, seed 0) from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 from a
+# 1 GiB copy), keyed by the hash of the kernel sources they were taken with.
+TRAFFIC = {"1e071d0ae89bc2a0": 6.485e6 * 1024 * 2.0 + 2.488e4 * 1024}
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("gm_abi.hip", "gm_kernels.h", "gm_device.h"):
+        with open(os.path.join(ROOT, "paper_2404_07780_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 WORKLOADS = {
     "uneven": dict(n=8192, desc="8192 single-Sersic galaxies, square cutouts log-uniform 48-256 px, per-galaxy "
                                 "Moffat PSF 25x25, Poisson + 5 e- read noise, LM from moment-based start"),
@@ -113,6 +128,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="galaxies (default: the workload's size)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle sample size (0 = skip)")
+    ap.add_argument("--calib", action="store_true",
+                    help="first run one 1 GiB device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fitter shards by galaxy with no communication, "
@@ -122,6 +139,13 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
+        del src, dst
     wl = WORKLOADS[args.workload]
     n = args.n or wl["n"]
     t0 = time.perf_counter()
@@ -198,7 +222,10 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "n_gal": n, "init": "default (moments)",
                    "max_iter": 100, "step_tol": 1e-4},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": (TRAFFIC.get(kernel_hash()) if (args.workload == "uneven" and n == 8192
+                                                               and args.seed == 0) else None),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "lm_fit_kernel", "kernel_ms": fit_s * 1e3,
                      "flops_per_launch": flops_fit},
         "breakdown_ms": {"default_guess": float(np.mean(guess_ms)), "lm_fit": float(np.mean(fit_ms)),

@@ -1,13 +1,20 @@
-"""Build libgmfit.so (the HIP library) in-tree for gfx950 with hipcc."""
+"""Build libgmfit.so (the HIP library) in-tree for gfx950 with hipcc.
+
+Each model family is its own translation unit; they are compiled to objects
+in parallel and linked into one shared library.
+"""
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "gm_abi.hip")
+CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libgmfit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -18,23 +25,42 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, SRC]
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out, file=sys.stderr)
-    os.replace(tmp, LIB)
+    return res.returncode, out
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    os.makedirs(LIB_DIR, exist_ok=True)
+    jobs = jobs or min(len(os.sched_getaffinity(0)), 16)
+    with tempfile.TemporaryDirectory(prefix="gmfit_build_") as tmp:
+        objs, cmds = [], []
+        for src in sources():
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append([HIPCC, *FLAGS, "-c", "-o", obj, src])
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(_run, cmds))
+        for cmd, (rc, out) in zip(cmds, results):
+            if rc != 0:
+                raise RuntimeError(f"hipcc failed on {cmd[-1]} ({rc}):\n{out}")
+            if verbose and out.strip():
+                print(out, file=sys.stderr)
+        tmp_lib = LIB + ".tmp"
+        rc, out = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib, *objs])
+        if rc != 0:
+            raise RuntimeError(f"link failed ({rc}):\n{out}")
+    os.replace(tmp_lib, LIB)
     return LIB
 
 

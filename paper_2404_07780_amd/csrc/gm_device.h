@@ -198,233 +198,533 @@ __device__ inline void geometry_derivs(const Geo &g, const Pt<F64> &p, float I, 
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// ---------------------------------------------------------------- components
+// Every component type provides: its LM slots (NS, kind(s)), the slots of
+// its axis ratio, angle and scales (canonical form), an FP64 prologue
+// prep(us, cst, ...) from its slot values us (u-space) and shape constants cst,
+// a point evaluation pt<F64>(k, dx, dy, I, d) of the light I (FP64 if F64)
+// and its FP32 derivatives d[s] = dI/du_s, and the moment-based start values.
+
 // Sersic (Sec. 4.1): I = I_e exp(-b [(r/r_e)^(1/n) - 1]),
-// I_e = F b^(2n) / (2 pi q r_e^2 n Gamma(2n) e^b).
-// Derivatives (FP32): dI/d{x0, y0, mag, ln r_e, ln n, q, theta}.
-struct SersicK {
-    Geo g;
-    double lnIe, b, inv2n, lnre2;
-    float lnIe2f, bf, b2f, inv2nf, l2re2f, bnf, cnf, nbpf, bl2nf;
-    static constexpr int ND = 7;
-};
-
-// All lanes of wave 0 call this (the b_n series is spread over the lanes).
-__device__ inline void sersic_prep(const double *u, double m0, int H, int W, int osf, int osw, int lane, SersicK &k)
-{
-    double x0 = u[0], y0 = u[1], m = u[2], lnre = u[3], lnn = u[4], q = u[5], th = u[6];
-    double n = exp(lnn);
-    double bp;
-    double b = sersic_b_wave(n, lane, &bp);
-    double psi = digamma(2.0 * n);
-    double lnIe = -0.4 * kLn10 * (m - m0) + 2.0 * n * log(b) - log(2.0 * kPi * q * n) - 2.0 * lnre
-                  - lgamma(2.0 * n) - b;
-    geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
-    k.lnIe = lnIe;
-    k.b = b;
-    k.inv2n = 0.5 / n;
-    k.lnre2 = 2.0 * lnre;
-    k.lnIe2f = (float)(lnIe * kLog2e);
-    k.bf = (float)b;
-    k.b2f = (float)(b * kLog2e);
-    k.inv2nf = (float)(0.5 / n);
-    k.l2re2f = (float)(2.0 * lnre * kLog2e);
-    k.bnf = (float)(b / n);
-    // d ln I / d ln n = cn - n b' z + b z ln(r^2/re^2) / (2n)
-    k.cnf = (float)(n * (2.0 * log(b) + 2.0 * n * bp / b - 2.0 * psi) - 1.0);
-    k.nbpf = (float)(n * bp);
-    k.bl2nf = (float)(b * kLn2 / (2.0 * n));
-}
-
-template <bool F64>
-__device__ inline void sersic_pt(const SersicK &k, double dx, double dy, double &I64, float *d)
-{
-    Pt<F64> p = frame<F64>(k.g, dx, dy);
-    float I, z, L2;
-    if constexpr (F64) {
-        double L = log(p.r2) - k.lnre2;                  // ln(r^2 / r_e^2)
-        double zd = exp(L * k.inv2n);                    // (r / r_e)^(1/n)
-        I64 = exp(k.lnIe - k.b * (zd - 1.0));
-        I = (float)I64;
-        z = (float)zd;
-        L2 = (float)(L * kLog2e);
-    } else {
-        L2 = __log2f(p.r2f) - k.l2re2f;
-        z = exp2f(L2 * k.inv2nf);
-        I = exp2f(k.lnIe2f - k.b2f * (z - 1.0f));
-        I64 = I;
+// I_e = F b^(2n) / (2 pi q r_e^2 n Gamma(2n) e^b).  Slots x0 y0 mag ln r_e ln n q theta.
+struct Sersic {
+    struct K {
+        Geo g;
+        double lnIe, b, inv2n, lnre2;
+        float bf, inv2nf, l2re2f, lnIe2f, b2f, bnf, cnf, nbpf, bl2nf;
+    };
+    static constexpr int NS = 7, IQ = 5, ITH = 6, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s)
+    {
+        return s == 0 ? KX0 : s == 1 ? KY0 : s == 2 ? KMAG : s == 3 ? KSCALE : s == 4 ? KN : s == 5 ? KQ : KPA;
     }
-    float dl = -k.bf * z * k.inv2nf * frcp(p.r2f);     // d ln I / d r^2
-    float gd[4];
-    geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
-    d[0] = gd[0];
-    d[1] = gd[1];
-    d[2] = kDMag * I;
-    d[3] = I * (-2.0f + k.bnf * z);
-    d[4] = I * (k.cnf - k.nbpf * z + k.bl2nf * z * L2);
-    d[5] = gd[2];
-    d[6] = gd[3];
-}
+    // all lanes of wave 0 call this (the b_n series is spread over the lanes)
+    __device__ static void prep(const double *u, const double *, double m0, int H, int W, int osf, int osw, int lane,
+                                K &k)
+    {
+        double x0 = u[0], y0 = u[1], m = u[2], lnre = u[3], lnn = u[4], q = u[5], th = u[6];
+        double n = exp(lnn);
+        double bp;
+        double b = sersic_b_wave(n, lane, &bp);
+        double psi = digamma(2.0 * n);
+        double lnIe = -0.4 * kLn10 * (m - m0) + 2.0 * n * log(b) - log(2.0 * kPi * q * n) - 2.0 * lnre
+                      - lgamma(2.0 * n) - b;
+        geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
+        k.lnIe = lnIe;
+        k.b = b;
+        k.inv2n = 0.5 / n;
+        k.lnre2 = 2.0 * lnre;
+        k.lnIe2f = (float)(lnIe * kLog2e);
+        k.bf = (float)b;
+        k.b2f = (float)(b * kLog2e);
+        k.inv2nf = (float)(0.5 / n);
+        k.l2re2f = (float)(2.0 * lnre * kLog2e);
+        k.bnf = (float)(b / n);
+        // d ln I / d ln n = cn - n b' z + b z ln(r^2/re^2) / (2n)
+        k.cnf = (float)(n * (2.0 * log(b) + 2.0 * n * bp / b - 2.0 * psi) - 1.0);
+        k.nbpf = (float)(n * bp);
+        k.bl2nf = (float)(b * kLn2 / (2.0 * n));
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float I, z, L2;
+        if constexpr (F64) {
+            double L = log(p.r2) - k.lnre2;                  // ln(r^2 / r_e^2)
+            double zd = exp(L * k.inv2n);                    // (r / r_e)^(1/n)
+            I64 = exp(k.lnIe - k.b * (zd - 1.0));
+            I = (float)I64;
+            z = (float)zd;
+            L2 = (float)(L * kLog2e);
+        } else {
+            L2 = __log2f(p.r2f) - k.l2re2f;
+            z = exp2f(L2 * k.inv2nf);
+            I = exp2f(k.lnIe2f - k.b2f * (z - 1.0f));
+            I64 = I;
+        }
+        float dl = -k.bf * z * k.inv2nf * frcp(p.r2f);     // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + k.bnf * z);
+        d[4] = I * (k.cnf - k.nbpf * z + k.bl2nf * z * L2);
+        d[5] = gd[2];
+        d[6] = gd[3];
+    }
+    // natural start values: r_e = r0 (r0 / 2 next to another component), n = 2 (4)
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double, int nrad,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = m; v[3] = nrad > 1 ? 0.5 * r0 : r0; v[4] = nrad > 1 ? 4.0 : 2.0;
+        v[5] = q0; v[6] = pa0;
+    }
+};
 
 // Exponential disk (Sec. 4.2.1): I = I0 exp(-r / r_s), I0 = F / (2 pi q r_s^2).
-// Derivatives: dI/d{x0, y0, mag, ln r_s, q, theta}.
-struct ExpDiskK {
-    Geo g;
-    double lnI0, irs;
-    float lnI02f, irsf, irs2f;
-    static constexpr int ND = 6;
+// Slots x0 y0 mag ln r_s q theta.
+struct ExpDisk {
+    struct K {
+        Geo g;
+        double lnI0, irs;
+        float lnI02f, irsf, irs2f;
+    };
+    static constexpr int NS = 6, IQ = 4, ITH = 5, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s)
+    {
+        return s == 0 ? KX0 : s == 1 ? KY0 : s == 2 ? KMAG : s == 3 ? KSCALE : s == 4 ? KQ : KPA;
+    }
+    __device__ static void prep(const double *u, const double *, double m0, int H, int W, int osf, int osw, int,
+                                K &k)
+    {
+        double x0 = u[0], y0 = u[1], m = u[2], lnrs = u[3], q = u[4], th = u[5];
+        double lnI0 = -0.4 * kLn10 * (m - m0) - log(2.0 * kPi * q) - 2.0 * lnrs;
+        geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
+        k.lnI0 = lnI0;
+        k.irs = exp(-lnrs);
+        k.lnI02f = (float)(lnI0 * kLog2e);
+        k.irsf = (float)k.irs;
+        k.irs2f = (float)(k.irs * kLog2e);
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float I, r;
+        if constexpr (F64) {
+            double rd = sqrt(p.r2);
+            I64 = exp(k.lnI0 - rd * k.irs);
+            I = (float)I64;
+            r = (float)rd;
+        } else {
+            r = __builtin_amdgcn_sqrtf(p.r2f);
+            I = exp2f(k.lnI02f - r * k.irs2f);
+            I64 = I;
+        }
+        float dl = -0.5f * k.irsf * frcp(r);                // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + r * k.irsf);
+        d[4] = gd[2];
+        d[5] = gd[3];
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double, int,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = m; v[3] = r0 / 1.678347; v[4] = q0; v[5] = pa0;
+    }
 };
 
-__device__ inline void expdisk_prep(const double *u, double m0, int H, int W, int osf, int osw, ExpDiskK &k)
-{
-    double x0 = u[0], y0 = u[1], m = u[2], lnrs = u[3], q = u[4], th = u[5];
-    double lnI0 = -0.4 * kLn10 * (m - m0) - log(2.0 * kPi * q) - 2.0 * lnrs;
-    geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
-    k.lnI0 = lnI0;
-    k.irs = exp(-lnrs);
-    k.lnI02f = (float)(lnI0 * kLog2e);
-    k.irsf = (float)k.irs;
-    k.irs2f = (float)(k.irs * kLog2e);
-}
-
-template <bool F64>
-__device__ inline void expdisk_pt(const ExpDiskK &k, double dx, double dy, double &I64, float *d)
-{
-    Pt<F64> p = frame<F64>(k.g, dx, dy);
-    float I, r;
-    if constexpr (F64) {
-        double rd = sqrt(p.r2);
-        I64 = exp(k.lnI0 - rd * k.irs);
-        I = (float)I64;
-        r = (float)rd;
-    } else {
-        r = __builtin_amdgcn_sqrtf(p.r2f);
-        I = exp2f(k.lnI02f - r * k.irs2f);
-        I64 = I;
+// Modified Ferrer (Sec. 4.2.2): I = I0 [1 - (r/r_out)^(2-b)]^a inside r_out, 0
+// beyond; I0 = F / (pi q r_out^2 a beta(a, 1 + 2/(2-b))).  Shape constants
+// cst = {a, b}.  Slots x0 y0 mag ln r_out q theta.
+struct Ferrer {
+    struct K {
+        Geo g;
+        double lnI0, a, e2, lnro2;          // e2 = (2 - b) / 2
+        float af, ef, iro2f;
+    };
+    static constexpr int NS = 6, IQ = 4, ITH = 5, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s) { return ExpDisk::kind(s); }
+    __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw, int,
+                                K &k)
+    {
+        double x0 = u[0], y0 = u[1], m = u[2], lnro = u[3], q = u[4], th = u[5];
+        double a = cst[0], bb = cst[1], c2 = 1.0 + 2.0 / (2.0 - bb);
+        double lbeta = lgamma(a) + lgamma(c2) - lgamma(a + c2);
+        geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
+        k.lnI0 = -0.4 * kLn10 * (m - m0) - log(kPi * q * a) - 2.0 * lnro - lbeta;
+        k.a = a;
+        k.e2 = 0.5 * (2.0 - bb);
+        k.lnro2 = 2.0 * lnro;
+        k.af = (float)a;
+        k.ef = (float)(2.0 - bb);
+        k.iro2f = (float)exp(-2.0 * lnro);
     }
-    float dl = -0.5f * k.irsf * frcp(r);                // d ln I / d r^2
-    float gd[4];
-    geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
-    d[0] = gd[0];
-    d[1] = gd[1];
-    d[2] = kDMag * I;
-    d[3] = I * (-2.0f + r * k.irsf);
-    d[4] = gd[2];
-    d[5] = gd[3];
-}
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float I, u, omu;
+        if constexpr (F64) {
+            double lnu = k.e2 * (log(p.r2) - k.lnro2);     // ln (r/r_out)^(2-b)
+            if (lnu >= 0.0) {
+                I64 = 0.0;
+                for (int s = 0; s < NS; ++s) d[s] = 0.0f;
+                return;
+            }
+            double omud = -expm1(lnu);
+            I64 = exp(k.lnI0 + k.a * log(omud));
+            I = (float)I64;
+            u = (float)exp(lnu);
+            omu = (float)omud;
+        } else {
+            float lnu = 0.5f * k.ef * __logf(p.r2f * k.iro2f);
+            if (lnu >= 0.0f) {
+                I64 = 0.0;
+                for (int s = 0; s < NS; ++s) d[s] = 0.0f;
+                return;
+            }
+            omu = -expm1f(lnu);
+            u = 1.0f - omu;
+            I = __expf((float)k.lnI0 + k.af * __logf(omu));
+            I64 = I;
+        }
+        float dl = -k.af * k.ef * u * frcp(2.0f * p.r2f * omu);   // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + k.af * k.ef * u * frcp(omu));
+        d[4] = gd[2];
+        d[5] = gd[3];
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double, int,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = m; v[3] = r0; v[4] = q0; v[5] = pa0;
+    }
+};
+
+// Empirical King (Sec. 4.2.3, eq. (BE_S) with the terms of the second bracket
+// in the order that gives I(0) = I0 and I(r_t) = 0):
+// I = I0 [(S - A) / (1 - A)]^alpha, S = (1 + r^2/r_c^2)^(-1/alpha),
+// A = (1 + r_t^2/r_c^2)^(-1/alpha); 0 beyond r_t.  cst = {alpha}.
+// Slots x0 y0 I0 ln r_c ln r_t q theta.
+struct King {
+    struct K {
+        Geo g;
+        double I0, al, ial, irc2, A, rt2;
+        float I0f, alf, ialf, irc2f, Af, dA_rcf, rt2f;
+    };
+    static constexpr int NS = 7, IQ = 5, ITH = 6, IS0 = 3, IS1 = 4;
+    __host__ __device__ static constexpr int kind(int s)
+    {
+        return s == 0 ? KX0 : s == 1 ? KY0 : s == 2 ? KAMP : s == 3 ? KSCALE : s == 4 ? KSCALE : s == 5 ? KQ : KPA;
+    }
+    __device__ static void prep(const double *u, const double *cst, double, int H, int W, int osf, int osw, int,
+                                K &k)
+    {
+        double x0 = u[0], y0 = u[1], I0 = u[2], lnrc = u[3], lnrt = u[4], q = u[5], th = u[6];
+        double al = cst[0];
+        double rc = exp(lnrc), rt = exp(lnrt);
+        double T = 1.0 + (rt / rc) * (rt / rc);
+        geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
+        k.I0 = I0;
+        k.al = al;
+        k.ial = 1.0 / al;
+        k.irc2 = 1.0 / (rc * rc);
+        k.A = pow(T, -1.0 / al);
+        k.rt2 = rt * rt;
+        k.I0f = (float)I0;
+        k.alf = (float)al;
+        k.ialf = (float)(1.0 / al);
+        k.irc2f = (float)k.irc2;
+        k.Af = (float)k.A;
+        k.dA_rcf = (float)(2.0 * k.A * (T - 1.0) / (al * T));     // dA / d ln r_c
+        k.rt2f = (float)k.rt2;
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float shape, s, S, D;
+        if constexpr (F64) {
+            if (p.r2 >= k.rt2) {
+                I64 = 0.0;
+                for (int q = 0; q < NS; ++q) d[q] = 0.0f;
+                return;
+            }
+            double sd = 1.0 + p.r2 * k.irc2;
+            double Sd = exp(-k.ial * log(sd));
+            double Dd = Sd - k.A;
+            double shd = exp(k.al * log(Dd / (1.0 - k.A)));
+            I64 = k.I0 * shd;
+            shape = (float)shd;
+            s = (float)sd;
+            S = (float)Sd;
+            D = (float)Dd;
+        } else {
+            if (p.r2f >= k.rt2f) {
+                I64 = 0.0;
+                for (int q = 0; q < NS; ++q) d[q] = 0.0f;
+                return;
+            }
+            s = 1.0f + p.r2f * k.irc2f;
+            S = __expf(-k.ialf * __logf(s));
+            D = S - k.Af;
+            shape = __expf(k.alf * __logf(D / (1.0f - k.Af)));
+            I64 = k.I0f * shape;
+        }
+        float I = k.I0f * shape;
+        float iD = frcp(D), iomA = frcp(1.0f - k.Af);
+        float dl = -S * k.irc2f * frcp(s) * iD;              // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, 0.0f, gd);
+        float dS_rc = 2.0f * S * (s - 1.0f) * k.ialf * frcp(s);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = shape;
+        d[3] = I * k.alf * (k.dA_rcf * iomA + (dS_rc - k.dA_rcf) * iD);
+        d[4] = I * k.alf * (-k.dA_rcf * iomA + k.dA_rcf * iD);
+        d[5] = gd[2];
+        d[6] = gd[3];
+    }
+    __device__ static void guess(double xc, double yc, double, double r0, double q0, double pa0, double pk, int,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = pk; v[3] = 0.5 * r0; v[4] = 4.0 * r0; v[5] = q0; v[6] = pa0;
+    }
+};
+
+// Gaussian (Sec. 4.2.4): I = I0 exp(-r^2 / (2 sigma^2)), FWHM = 2 sqrt(2 ln 2) sigma.
+// Slots x0 y0 I0 ln fwhm q theta.
+struct Gaussian {
+    struct K {
+        Geo g;
+        double I0, i2s2;
+        float I0f, i2s2f;
+    };
+    static constexpr int NS = 6, IQ = 4, ITH = 5, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s)
+    {
+        return s == 0 ? KX0 : s == 1 ? KY0 : s == 2 ? KAMP : s == 3 ? KSCALE : s == 4 ? KQ : KPA;
+    }
+    __device__ static void prep(const double *u, const double *, double, int H, int W, int osf, int osw, int, K &k)
+    {
+        double sg = exp(u[3]) / (2.0 * sqrt(2.0 * kLn2));
+        geo_prep(u[0], u[1], u[4], u[5], H, W, osf, osw, k.g);
+        k.I0 = u[2];
+        k.i2s2 = 0.5 / (sg * sg);
+        k.I0f = (float)u[2];
+        k.i2s2f = (float)k.i2s2;
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float shape;
+        if constexpr (F64) {
+            double shd = exp(-p.r2 * k.i2s2);
+            I64 = k.I0 * shd;
+            shape = (float)shd;
+        } else {
+            shape = __expf(-p.r2f * k.i2s2f);
+            I64 = k.I0f * shape;
+        }
+        float I = k.I0f * shape;
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, -k.i2s2f, 0.0f, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = shape;
+        d[3] = I * 2.0f * p.r2f * k.i2s2f;
+        d[4] = gd[2];
+        d[5] = gd[3];
+    }
+    __device__ static void guess(double xc, double yc, double, double r0, double q0, double pa0, double pk, int,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = pk; v[3] = r0; v[4] = q0; v[5] = pa0;
+    }
+};
+
+// Moffat (Sec. 4.2.5): I = I0 [1 + (r/r_d)^2]^(-beta),
+// r_d = FWHM / (2 sqrt(2^(1/beta) - 1)), I0 = (beta - 1) F / (pi q r_d^2).
+// cst = {beta}.  Slots x0 y0 mag ln fwhm q theta.
+struct Moffat {
+    struct K {
+        Geo g;
+        double lnI0, be, ird2;
+        float bef, ird2f, rd2f;
+    };
+    static constexpr int NS = 6, IQ = 4, ITH = 5, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s) { return ExpDisk::kind(s); }
+    __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw, int,
+                                K &k)
+    {
+        double be = cst[0];
+        double rd = exp(u[3]) / (2.0 * sqrt(pow(2.0, 1.0 / be) - 1.0));
+        geo_prep(u[0], u[1], u[4], u[5], H, W, osf, osw, k.g);
+        k.lnI0 = -0.4 * kLn10 * (u[2] - m0) + log(be - 1.0) - log(kPi * u[4] * rd * rd);
+        k.be = be;
+        k.ird2 = 1.0 / (rd * rd);
+        k.bef = (float)be;
+        k.ird2f = (float)k.ird2;
+        k.rd2f = (float)(rd * rd);
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float I;
+        if constexpr (F64) {
+            I64 = exp(k.lnI0 - k.be * log1p(p.r2 * k.ird2));
+            I = (float)I64;
+        } else {
+            I = __expf((float)k.lnI0 - k.bef * __logf(1.0f + p.r2f * k.ird2f));
+            I64 = I;
+        }
+        float idn = frcp(k.rd2f + p.r2f);
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, -k.bef * idn, -k.g.iqf, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + 2.0f * k.bef * p.r2f * idn);
+        d[4] = gd[2];
+        d[5] = gd[3];
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double, int,
+                                 double *v)
+    {
+        v[0] = xc; v[1] = yc; v[2] = m; v[3] = r0; v[4] = q0; v[5] = pa0;
+    }
+};
 
 // ---------------------------------------------------------------- families
 // A family fixes, at compile time, the components of a model, the layout of
-// the internal LM vector u and the image planes: plane 0 is the summed
-// convolved light (FP64), plane 1 + k the derivative with respect to u_k
+// the internal LM vector u and the image planes: plane 0 is the summed light
+// of the components (FP64), plane 1 + k the derivative with respect to u_k
 // (FP32; sky, the last entry of u, has the constant derivative 1 and no plane).
 
-// Single Sersic + sky. u = x0 y0 mag ln r_e ln n q theta sky.
-struct FamSersic {
-    static constexpr int P = 8, NPL = 8, NCOMP = 1, SKY = 7;
-    static constexpr int ND = SersicK::ND;             // derivative values per window pixel
-    __host__ __device__ static constexpr int kind(int k)
-    {
-        return k == 0 ? KX0 : k == 1 ? KY0 : k == 2 ? KMAG : k == 3 ? KSCALE : k == 4 ? KN
-             : k == 5 ? KQ : k == 6 ? KPA : KSKY;
-    }
+// One component + sky: u = the component's slots, then sky.
+template <class C>
+struct FamSingle {
+    static constexpr int P = C::NS + 1, NPL = P, NCOMP = 1, NRAD = 1, SKY = C::NS, ND = C::NS;
+    __host__ __device__ static constexpr int kind(int k) { return k < C::NS ? C::kind(k) : KSKY; }
     struct Prep {
-        SersicK s;
+        typename C::K k0;
         double sky;
     };
-    __device__ static void prep(const double *u, double m0, int H, int W, int osf, int osw, int lane, Prep &p)
+    __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw,
+                                int lane, Prep &p)
     {
-        sersic_prep(u, m0, H, W, osf, osw, lane, p.s);
-        p.sky = u[7];
+        C::prep(u, cst, m0, H, W, osf, osw, lane, p.k0);
+        p.sky = u[SKY];
     }
-    __device__ static const Geo &geo(const Prep &p, int) { return p.s.g; }
+    __device__ static const Geo &geo(const Prep &p, int) { return p.k0.g; }
     template <bool F64>
     __device__ static void comp_pt(const Prep &p, int, double dx, double dy, double &I, float *d)
     {
-        sersic_pt<F64>(p.s, dx, dy, I, d);
+        C::template pt<F64>(p.k0, dx, dy, I, d);
     }
-    // add component c's derivatives into the derivative planes (index = plane - 1)
+    // component derivatives into the derivative planes (index = plane - 1)
     __device__ static void scatter(int, const float *d, float *dp)
     {
 #pragma unroll
-        for (int i = 0; i < 7; ++i) dp[i] += d[i];
+        for (int i = 0; i < C::NS; ++i) dp[i] += d[i];
     }
-    // start vector from image moments: centre, magnitude, radius, axis ratio,
-    // PA (deg), border sky; n = 2 for a lone Sersic
-    __device__ static void default_guess(double xc, double yc, double mg, double r0, double q0, double pa0,
-                                         double sky0, double, double *nat)
+    __device__ static void default_guess(double xc, double yc, double m, double r0, double q0, double pa0,
+                                         double sky0, double pk, double *nat)
     {
-        nat[0] = xc; nat[1] = yc; nat[2] = mg; nat[3] = r0; nat[4] = 2.0; nat[5] = q0; nat[6] = pa0; nat[7] = sky0;
+        C::guess(xc, yc, m, r0, q0, pa0, pk, NRAD, nat);
+        nat[SKY] = sky0;
     }
-    // canonical form: (q index, theta index, scale indices)
     static constexpr int NCAN = 1;
     __host__ __device__ static void canon(int, int &iq, int &ith, int &is0, int &is1)
     {
-        iq = 5; ith = 6; is0 = 3; is1 = -1;
+        iq = C::IQ; ith = C::ITH; is0 = C::IS0; is1 = C::IS1;
     }
 };
 
-// Sersic bulge + exponential disk with a shared centre + sky.
-// u = x0 y0 | mag_b ln r_e ln n q_b theta_b | mag_d ln r_s q_d theta_d | sky.
-struct FamBulgeDisk {
-    static constexpr int P = 12, NPL = 12, NCOMP = 2, SKY = 11;
-    static constexpr int ND = SersicK::ND;             // the larger of the two
+// Two components with a shared centre + sky:
+// u = x0 y0 | C1 slots 2.. | C2 slots 2.. | sky.  cst: C1's constants at
+// cst[0..1], C2's at cst[2..3].
+template <class C1, class C2>
+struct FamPair {
+    static constexpr int O2 = C1::NS - 2;                  // C2 slot s >= 2 sits at u[O2 + s]
+    static constexpr int P = C1::NS + C2::NS - 2 + 1, NPL = P, NCOMP = 2, NRAD = 2, SKY = P - 1;
+    static constexpr int ND = C1::NS > C2::NS ? C1::NS : C2::NS;
     __host__ __device__ static constexpr int kind(int k)
     {
-        return k == 0 ? KX0 : k == 1 ? KY0 : k == 2 ? KMAG : k == 3 ? KSCALE : k == 4 ? KN
-             : k == 5 ? KQ : k == 6 ? KPA : k == 7 ? KMAG : k == 8 ? KSCALE : k == 9 ? KQ
-             : k == 10 ? KPA : KSKY;
+        return k < C1::NS ? C1::kind(k) : k < SKY ? C2::kind(k - O2) : KSKY;
     }
     struct Prep {
-        SersicK s;
-        ExpDiskK e;
+        typename C1::K k0;
+        typename C2::K k1;
         double sky;
     };
-    __device__ static void prep(const double *u, double m0, int H, int W, int osf, int osw, int lane, Prep &p)
+    __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw,
+                                int lane, Prep &p)
     {
-        sersic_prep(u, m0, H, W, osf, osw, lane, p.s);
-        double ue[6] = {u[0], u[1], u[7], u[8], u[9], u[10]};
-        expdisk_prep(ue, m0, H, W, osf, osw, p.e);
-        p.sky = u[11];
+        C1::prep(u, cst, m0, H, W, osf, osw, lane, p.k0);
+        double u2[C2::NS];
+        u2[0] = u[0];
+        u2[1] = u[1];
+        for (int s = 2; s < C2::NS; ++s) u2[s] = u[O2 + s];
+        C2::prep(u2, cst + 2, m0, H, W, osf, osw, lane, p.k1);
+        p.sky = u[SKY];
     }
-    __device__ static const Geo &geo(const Prep &p, int c) { return c == 0 ? p.s.g : p.e.g; }
+    __device__ static const Geo &geo(const Prep &p, int c) { return c == 0 ? p.k0.g : p.k1.g; }
     template <bool F64>
     __device__ static void comp_pt(const Prep &p, int c, double dx, double dy, double &I, float *d)
     {
-        if (c == 0) {
-            sersic_pt<F64>(p.s, dx, dy, I, d);
-        } else {
-            expdisk_pt<F64>(p.e, dx, dy, I, d);
-            d[6] = 0.0f;
-        }
+        if (c == 0) C1::template pt<F64>(p.k0, dx, dy, I, d);
+        else C2::template pt<F64>(p.k1, dx, dy, I, d);
     }
     __device__ static void scatter(int c, const float *d, float *dp)
     {
         if (c == 0) {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) dp[i] += d[i];
+            for (int i = 0; i < C1::NS; ++i) dp[i] += d[i];
         } else {
             dp[0] += d[0];
             dp[1] += d[1];
 #pragma unroll
-            for (int i = 2; i < 6; ++i) dp[5 + i] += d[i];   // planes 8..11 = u 7..10
+            for (int i = 2; i < C2::NS; ++i) dp[O2 + i] += d[i];
         }
     }
-    // the flux is split evenly; bulge n = 4, r_e = r0 / 2; disk r_s = r0 / b_1
-    __device__ static void default_guess(double xc, double yc, double mg, double r0, double q0, double pa0,
-                                         double sky0, double, double *nat)
+    __device__ static void default_guess(double xc, double yc, double m, double r0, double q0, double pa0,
+                                         double sky0, double pk, double *nat)
     {
-        double ms = mg + 2.5 * log10(2.0);
-        nat[0] = xc; nat[1] = yc;
-        nat[2] = ms; nat[3] = 0.5 * r0; nat[4] = 4.0; nat[5] = q0; nat[6] = pa0;
-        nat[7] = ms; nat[8] = r0 / 1.678347; nat[9] = q0; nat[10] = pa0;
-        nat[11] = sky0;
+        double v2[C2::NS];
+        C1::guess(xc, yc, m, r0, q0, pa0, pk, NRAD, nat);
+        C2::guess(xc, yc, m, r0, q0, pa0, pk, NRAD, v2);
+        for (int s = 2; s < C2::NS; ++s) nat[O2 + s] = v2[s];
+        nat[SKY] = sky0;
     }
     static constexpr int NCAN = 2;
     __host__ __device__ static void canon(int c, int &iq, int &ith, int &is0, int &is1)
     {
-        if (c == 0) { iq = 5; ith = 6; is0 = 3; is1 = -1; }
-        else { iq = 9; ith = 10; is0 = 8; is1 = -1; }
+        if (c == 0) {
+            iq = C1::IQ; ith = C1::ITH; is0 = C1::IS0; is1 = C1::IS1;
+        } else {
+            iq = O2 + C2::IQ; ith = O2 + C2::ITH;
+            is0 = C2::IS0 >= 2 ? O2 + C2::IS0 : -1;
+            is1 = C2::IS1 >= 2 ? O2 + C2::IS1 : -1;
+        }
     }
 };
+
+using FamSersic = FamSingle<Sersic>;
+using FamBulgeDisk = FamPair<Sersic, ExpDisk>;
+using FamSersicBar = FamPair<Sersic, Ferrer>;
 
 }  // namespace gm

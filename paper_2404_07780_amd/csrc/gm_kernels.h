@@ -48,8 +48,10 @@ struct ModelArgs {
     int p;
     int col[MAXP];
     double fixedv[MAXP];
+    double cst[4];          // shape constants: component 0 at [0..1], component 1 at [2..3]
     double m0;
     int osf, osw;
+    int nflux;              // components whose magnitude/amplitude is fitted (start-vector flux split)
 };
 
 struct BatchArgs {
@@ -118,7 +120,7 @@ __device__ void eval_prologue(const double *u, const ModelArgs &ma, int H, int W
     const int tid = threadIdx.x;
     if (tid < 64) {
         typename F::Prep lp;
-        F::prep(u, ma.m0, H, W, ma.osf, ma.osw, tid, lp);
+        F::prep(u, ma.cst, ma.m0, H, W, ma.osf, ma.osw, tid, lp);
         if (tid == 0) sh.prep = lp;
     }
     __syncthreads();
@@ -144,7 +146,7 @@ __device__ void eval_prologue(const double *u, const ModelArgs &ma, int H, int W
             for (int s = 0; s < f; ++s) {
                 const double dx = ((double)j + ((double)s + 0.5) * invf) - g.x0;
                 double I;
-                float d[F::ND];
+                float d[F::ND] = {};
                 F::template comp_pt<true>(sh.prep, c, dx, dy, I, d);
                 aI += I;
 #pragma unroll
@@ -183,7 +185,7 @@ __device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, d
     for (int c = 0; c < F::NCOMP; ++c) {
         const Geo &g = F::geo(sh.prep, c);
         double I;
-        float d[F::ND];
+        float d[F::ND] = {};
         if (i >= g.wi0 && i <= g.wi1 && j >= g.wj0 && j <= g.wj1) {
             const int pix = (i - g.wi0) * (g.wj1 - g.wj0 + 1) + (j - g.wj0);
             I = sh.win0[c][pix];
@@ -995,7 +997,8 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
                 mo[3] = log(r0); mo[4] = q0; mo[5] = th0;
             }
             double nat[F::P];
-            F::default_guess(xc, yc, mg, r0, q0, pa0, sky0, pk > 0.0 ? pk : 1.0, nat);
+            const double ms = mg + 2.5 * log10((double)(ma.nflux > 1 ? ma.nflux : 1));
+            F::default_guess(xc, yc, ms, r0, q0, pa0, sky0, pk > 0.0 ? pk : 1.0, nat);
             double *out = ga.params + (int64_t)g * ma.p;
             for (int k = 0; k < F::P; ++k)
                 if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
@@ -1004,6 +1007,6 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
     }
 }
 
-__global__ void fill_int_kernel(int *p, int v) { *p = v; }
+static __global__ void fill_int_kernel(int *p, int v) { *p = v; }
 
 }  // namespace gm

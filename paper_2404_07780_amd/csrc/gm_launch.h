@@ -1,0 +1,258 @@
+// gm_launch.h -- host-side drivers of the kernels, templated on the model
+// family.  Each family is instantiated in a translation unit of its own
+// (gm_fam_*.hip) so that the families compile in parallel; gm_abi.hip reaches
+// them through a table of FamilyOps.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "gm_kernels.h"
+
+struct gm_ctx {
+    int device = 0;
+    int num_cu = 0;
+    void *dev = nullptr;          // grow-only device workspace
+    size_t dev_bytes = 0;
+    void *host = nullptr;         // pinned staging buffer
+    size_t host_bytes = 0;
+    hipEvent_t staged = nullptr;  // last copy out of the staging buffer
+    bool pending = false;
+    float *unit_psf = nullptr;    // device 1x1 kernel {1.0}: runs unconvolved models
+};
+
+namespace gm {
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+// Everything a driver needs besides the family: the caller's batch (host
+// metadata, device pixels), the matched model and whether the model is
+// convolved (an unconvolved model runs with the 1x1 unit PSF).
+struct CallInfo {
+    const gm_batch *b;
+    ModelArgs ma;
+    bool convolved;
+};
+
+// Device workspace of one call: [meta | extra | queue counter].
+struct Staged {
+    Meta *meta;
+    void *extra;
+    int *queue;
+};
+
+// defined in gm_abi.hip
+int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, hipStream_t st, Staged *out);
+int batch_kt(const CallInfo &ci);
+int max_k(const CallInfo &ci);
+
+inline int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_EHIP; }
+
+inline BatchArgs batch_args(gm_ctx *c, const CallInfo &ci, const Staged &sg)
+{
+    return BatchArgs{sg.meta, ci.b->data, ci.b->sigma, ci.convolved ? ci.b->psf : c->unit_psf, ci.b->omega};
+}
+
+template <class F>
+size_t static_lds()
+{
+    return sizeof(EvalShared<F>) + sizeof(LMShared<F>) + 64;
+}
+
+// Dynamic LDS for NG plane groups and PSF side K: the plane buffer, which also
+// hosts the window partial sums, the wave partial sums of the normal
+// equations and the thread-0 solver temporaries.
+template <class F, int NG>
+size_t lds_bytes(int K)
+{
+    return std::max({planes_bytes<F, NG>(K), (size_t)NWAVE * (1 + F::P + F::P * (F::P + 1) / 2) * 8,
+                     (size_t)3 * F::P * F::P * 8, window_scratch_bytes<F>()});
+}
+
+template <typename Kern>
+int prepare(Kern kern, size_t lds, int *blocks_per_cu)
+{
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return GM_EHIP;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds) != hipSuccess) return GM_EHIP;
+    *blocks_per_cu = std::max(nb, 1);
+    return GM_OK;
+}
+
+template <class F, int NG, int KT>
+int launch_fit(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArgs &fa, size_t lds, hipStream_t st)
+{
+    auto kern = lm_fit_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(fa.n_gal, per_cu * c->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, fa);
+    return hip_rc(hipGetLastError());
+}
+
+template <class F, int NG, int KT>
+int launch_err(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, hipStream_t st)
+{
+    auto kern = errors_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(ea.n_gal, per_cu * c->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, ea);
+    return hip_rc(hipGetLastError());
+}
+
+template <class F, int NG, int KT>
+int launch_img(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ImageArgs &ia, size_t lds, hipStream_t st)
+{
+    auto kern = image_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    int grid = std::min(ia.n_tiles, 4 * per_cu * c->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, ia);
+    return hip_rc(hipGetLastError());
+}
+
+// Dispatch on the batch's compile-time PSF side: KT0 first, then the others.
+template <class F, int NG, int... KTS>
+struct Dispatch;
+template <class F, int NG>
+struct Dispatch<F, NG> {
+    template <class... A> static int fit(int, A &&...a) { return launch_fit<F, NG, 0>(a...); }
+    template <class... A> static int err(int, A &&...a) { return launch_err<F, NG, 0>(a...); }
+    template <class... A> static int img(int, A &&...a) { return launch_img<F, NG, 0>(a...); }
+};
+template <class F, int NG, int K0, int... KR>
+struct Dispatch<F, NG, K0, KR...> {
+    template <class... A> static int fit(int kt, A &&...a)
+    {
+        return kt == K0 ? launch_fit<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::fit(kt, a...);
+    }
+    template <class... A> static int err(int kt, A &&...a)
+    {
+        return kt == K0 ? launch_err<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::err(kt, a...);
+    }
+    template <class... A> static int img(int kt, A &&...a)
+    {
+        return kt == K0 ? launch_img<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::img(kt, a...);
+    }
+};
+
+template <class F, int NG>
+int check_lds(int K, size_t *lds)
+{
+    *lds = lds_bytes<F, NG>(K);
+    return (*lds + static_lds<F>() <= kMaxLds) ? GM_OK : GM_EUNSUPPORTED;
+}
+
+template <class F, int NG, int... KTS>
+int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params, double *chi2, int32_t *niter,
+            int32_t *status, hipStream_t st)
+{
+    const gm_batch *b = ci.b;
+    size_t lds;
+    int rc = check_lds<F, NG>(max_k(ci), &lds);
+    if (rc) return rc;
+    // longest-processing-time order: biggest cutouts (times PSF area) first
+    std::vector<int> order(b->n_gal);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(b->n_gal);
+    for (int g = 0; g < b->n_gal; ++g) {
+        double k = ci.convolved ? b->psf_k[g] : 1.0;
+        cost[g] = (double)b->h[g] * b->w[g] * k * k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    Staged sg;
+    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)b->n_gal, st, &sg);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
+    if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    FitArgs fa{};
+    fa.order = reinterpret_cast<const int *>(sg.extra);
+    fa.n_gal = b->n_gal;
+    fa.queue = sg.queue;
+    fa.params = params;
+    fa.chi2 = chi2;
+    fa.niter = niter;
+    fa.status = status;
+    fa.max_iter = o ? o->max_iter : 100;
+    fa.lambda0 = o ? o->lambda0 : 1e-3;
+    fa.tol = o ? o->step_tol : 1e-4;
+    return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, st);
+}
+
+template <class F, int NG, int... KTS>
+int run_errors(gm_ctx *c, const CallInfo &ci, const double *params, double *err, double *cov, hipStream_t st)
+{
+    size_t lds;
+    int rc = check_lds<F, NG>(max_k(ci), &lds);
+    if (rc) return rc;
+    Staged sg;
+    rc = stage(c, ci, nullptr, 0, st, &sg);
+    if (rc) return rc;
+    ErrArgs ea{params, err, cov, ci.b->n_gal};
+    return Dispatch<F, NG, KTS...>::err(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ea, lds, st);
+}
+
+template <class F, int NG, int... KTS>
+int run_image(gm_ctx *c, const CallInfo &ci, const double *params, float *out, int mode, hipStream_t st)
+{
+    const gm_batch *b = ci.b;
+    size_t lds;
+    int rc = check_lds<F, NG>(max_k(ci), &lds);
+    if (rc) return rc;
+    std::vector<TileItem> tiles;
+    for (int g = 0; g < b->n_gal; ++g)
+        for (int ty = 0; ty < (b->h[g] + TILE - 1) / TILE; ++ty)
+            for (int tx = 0; tx < (b->w[g] + TILE - 1) / TILE; ++tx) tiles.push_back({g, ty, tx, 0});
+    Staged sg;
+    rc = stage(c, ci, tiles.data(), sizeof(TileItem) * tiles.size(), st, &sg);
+    if (rc) return rc;
+    ImageArgs ia{reinterpret_cast<const TileItem *>(sg.extra), (int)tiles.size(), params, out, mode};
+    return Dispatch<F, NG, KTS...>::img(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ia, lds, st);
+}
+
+template <class F>
+int run_guess(gm_ctx *c, const CallInfo &ci, double *params, double *moments, hipStream_t st)
+{
+    Staged sg;
+    int rc = stage(c, ci, nullptr, 0, st, &sg);
+    if (rc) return rc;
+    GuessArgs ga{params, moments, ci.b->n_gal};
+    int grid = std::min(ci.b->n_gal, 8 * c->num_cu);
+    hipLaunchKernelGGL(guess_kernel<F>, dim3(grid), dim3(NT), 0, st, ci.ma, batch_args(c, ci, sg), ga);
+    return hip_rc(hipGetLastError());
+}
+
+// Entry points of one family.
+struct FamilyOps {
+    int (*fit)(gm_ctx *, const CallInfo &, const gm_fit_opts *, double *, double *, int32_t *, int32_t *,
+               hipStream_t);
+    int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t);
+    int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t);
+    int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t);
+};
+
+template <class F, int NG, int... KTS>
+FamilyOps make_ops()
+{
+    return FamilyOps{run_fit<F, NG, KTS...>, run_errors<F, NG, KTS...>, run_image<F, NG, KTS...>, run_guess<F>};
+}
+
+// family tables, one per translation unit
+FamilyOps ops_sersic();
+FamilyOps ops_bulgedisk();
+FamilyOps ops_sersicbar();
+FamilyOps ops_expdisk();
+FamilyOps ops_ferrer();
+FamilyOps ops_king();
+FamilyOps ops_gaussian();
+FamilyOps ops_moffat();
+
+}  // namespace gm

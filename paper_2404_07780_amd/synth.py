@@ -63,9 +63,47 @@ MODEL_SPECS: Dict[str, dict] = {
         ],
         names=["x0", "y0", "mag_b", "re_b", "n_b", "q_b", "pa_b", "mag_d", "rs_d", "q_d", "pa_d", "sky"],
     ),
+    # Sersic + modified Ferrer bar (a = 0.5, b = 1.9 fixed), shared centre
+    "sersicbar": dict(
+        p=12,
+        comps=[
+            (SERSIC, 1, [0, 1, 2, 3, 4, 5, 6], []),
+            (FERRER, 1, [0, 1, 7, 8, 9, 10, -1, -1], [0, 0, 0, 0, 0, 0, 0.5, 1.9]),
+            (SKY, 0, [11], []),
+        ],
+        names=["x0", "y0", "mag", "re", "n", "q", "pa", "mag_bar", "rout", "q_bar", "pa_bar", "sky"],
+    ),
+    # circular King cluster (alpha = 2, q = 1, PA = 0 fixed)
+    "king": dict(
+        p=6,
+        comps=[
+            (KING, 1, [0, 1, 2, 3, 4, -1, -1, -1], [0, 0, 0, 0, 0, 1.0, 0.0, 2.0]),
+            (SKY, 0, [5], []),
+        ],
+        names=["x0", "y0", "I0", "rc", "rt", "sky"],
+    ),
+    # unconvolved circular Moffat point source (beta = 3, q = 1, PA = 0 fixed)
+    "point": dict(
+        p=5,
+        comps=[
+            (MOFFAT, 0, [0, 1, 2, 3, -1, -1, -1], [0, 0, 0, 0, 1.0, 0.0, 3.0]),
+            (SKY, 0, [4], []),
+        ],
+        names=["x0", "y0", "mag", "fwhm", "sky"],
+    ),
 }
 
-CONFIG_IDS = {"sersic64": 1, "uneven": 2, "bulgedisk": 3}
+# columns that carry a component's flux: ("mag", col) shift by -2.5 log10 F,
+# ("amp", col) scale by F
+FLUX_COLUMNS = {
+    "sersic": [("mag", 2)],
+    "bulgedisk": [("mag", 2), ("mag", 7)],
+    "sersicbar": [("mag", 2), ("mag", 7)],
+    "king": [("amp", 2)],
+    "point": [("mag", 2)],
+}
+
+CONFIG_IDS = {"sersic64": 1, "uneven": 2, "bulgedisk": 3, "mixed": 5}
 
 
 def _rng(seed: int, cfg: int, i: int, stream: int) -> np.random.Generator:
@@ -114,6 +152,7 @@ class Batch:
     seed: int = 0
     data: Optional[np.ndarray] = None    # float32, filled by finish()
     sigma: Optional[np.ndarray] = None
+    omega: Optional[np.ndarray] = None   # uint8 mask (1 = use), or None
 
     @property
     def n(self) -> int:
@@ -145,16 +184,9 @@ class Batch:
         if self.data is not None:
             out.data = np.concatenate([self.image(self.data, int(g)).ravel() for g in sel])
             out.sigma = np.concatenate([self.image(self.sigma, int(g)).ravel() for g in sel])
+        if self.omega is not None:
+            out.omega = np.concatenate([self.image(self.omega, int(g)).ravel() for g in sel])
         return out
-
-
-def _mag_columns(model: str) -> List[int]:
-    spec = MODEL_SPECS[model]
-    cols = []
-    for typ, _conv, idx, _fx in spec["comps"]:
-        if typ in (SERSIC, EXPDISK, FERRER, MOFFAT):
-            cols.append(idx[2])
-    return cols
 
 
 def _sersic_draw(r: np.random.Generator, h: int, w: int):
@@ -247,12 +279,11 @@ def unit_truth(b: Batch) -> np.ndarray:
 def finish(b: Batch, unit_images: np.ndarray) -> Batch:
     """Scale unit-flux noiseless renders to the drawn peak SNR, add sky and
     noise.  unit_images: concatenated float64/float32 pixels of the model
-    rendered at unit_truth(b).  Fills b.data, b.sigma and the magnitudes of
-    b.truth."""
+    rendered at unit_truth(b).  Fills b.data, b.sigma and the flux columns of
+    b.truth (magnitudes shifted, amplitudes scaled)."""
     cfg = CONFIG_IDS[b.config]
     data = np.empty(b.npix, np.float32)
     sigma = np.empty(b.npix, np.float32)
-    mag_cols = _mag_columns(b.model)
     for g in range(b.n):
         u = np.asarray(b.image(unit_images, g), np.float64)
         peak = float(u.max())
@@ -276,8 +307,100 @@ def finish(b: Batch, unit_images: np.ndarray) -> Batch:
         npx = u.size
         data[o:o + npx] = d.ravel()
         sigma[o:o + npx] = s.ravel()
-        for c in mag_cols:
-            b.truth[g, c] = b.truth[g, c] - 2.5 * math.log10(F)
+        for kind, c in FLUX_COLUMNS[b.model]:
+            if kind == "mag":
+                b.truth[g, c] = b.truth[g, c] - 2.5 * math.log10(F)
+            else:
+                b.truth[g, c] = b.truth[g, c] * F
     b.data = data
     b.sigma = sigma
     return b
+
+
+def _blob_mask(r: np.random.Generator, h: int, w: int, x0: float, y0: float, frac: float = 0.05) -> np.ndarray:
+    """Elliptical blobs (semi-major U(2, 8) px, q U(0.3, 1), random PA, centres
+    at least 5 px from (x0, y0)) added until at least `frac` of the pixels are
+    masked; returns the mask (1 = use)."""
+    xx = np.arange(w)[None, :] + 0.5
+    yy = h - np.arange(h)[:, None] - 0.5
+    m = np.ones((h, w), np.uint8)
+    for _ in range(1000):
+        if 1.0 - m.mean() >= frac:
+            break
+        a = r.uniform(2.0, 8.0)
+        q = r.uniform(0.3, 1.0)
+        th = math.radians(r.uniform(0.0, 180.0))
+        cx, cy = r.uniform(0.0, w), r.uniform(0.0, h)
+        if math.hypot(cx - x0, cy - y0) < 5.0:
+            continue
+        dx, dy = xx - cx, yy - cy
+        X = math.cos(th) * dx + math.sin(th) * dy
+        Y = -math.sin(th) * dx + math.cos(th) * dy
+        m[(X / a) ** 2 + (Y / (q * a)) ** 2 <= 1.0] = 0
+    return m
+
+
+MIXED_KINDS = ("sersic", "sersicbar", "king", "point")
+
+
+def draw_mixed(n: int, seed: int = 0, start: int = 0) -> Dict[str, Batch]:
+    """Mixed-profile workload, galaxies start..start+n-1: square cutouts
+    log-uniform in [64, 192] px; 60% single Sersic, 20% Sersic + Ferrer bar
+    (r_out U(5, 20) px, q U(0.2, 0.5), PA U(0, 180), bar flux fraction
+    U(0.1, 0.3)), 10% King (r_c U(1, 5) px, r_t U(10, 60) px with r_t >= 2 r_c),
+    10% unconvolved Moffat point source (FWHM that of the galaxy's PSF); a
+    25x25 Moffat PSF per galaxy and Poisson + read noise as in "uneven"; at
+    least 5% of the pixels masked in elliptical blobs.  Returns one batch per
+    model (keys of MIXED_KINDS present)."""
+    cfg = CONFIG_IDS["mixed"]
+    rows = {k: [] for k in MIXED_KINDS}
+    for i in range(start, start + n):
+        r = _rng(seed, cfg, i, 0)
+        side = int(round(math.exp(r.uniform(math.log(64.0), math.log(192.0)))))
+        h = w = side
+        u = r.uniform()
+        kind = "sersic" if u < 0.6 else "sersicbar" if u < 0.8 else "king" if u < 0.9 else "point"
+        beta = r.uniform(2.5, 4.5)
+        fwhm = r.uniform(1.2, 2.5)
+        psf = moffat_psf(beta, fwhm, 25)
+        sky = r.uniform(50.0, 200.0)
+        if kind == "sersic":
+            x0, y0, re, nn, q, pa, snr = _sersic_draw(r, h, w)
+            t = [x0, y0, M0, re, nn, q, pa, sky]
+        elif kind == "sersicbar":
+            x0, y0, re, nn, q, pa, snr = _sersic_draw(r, h, w)
+            rout = r.uniform(5.0, 20.0)
+            qb = r.uniform(0.2, 0.5)
+            pab = r.uniform(0.0, 180.0)
+            fb = r.uniform(0.1, 0.3)
+            t = [x0, y0, M0 - 2.5 * math.log10(1.0 - fb), re, nn, q, pa, M0 - 2.5 * math.log10(fb), rout, qb, pab,
+                 sky]
+        elif kind == "king":
+            x0 = w / 2.0 + r.uniform(-2.0, 2.0)
+            y0 = h / 2.0 + r.uniform(-2.0, 2.0)
+            rc = r.uniform(1.0, 5.0)
+            rt = max(r.uniform(10.0, 60.0), 2.0 * rc)
+            snr = math.exp(r.uniform(math.log(20.0), math.log(200.0)))
+            t = [x0, y0, 1.0, rc, rt, sky]
+        else:
+            x0 = w / 2.0 + r.uniform(-2.0, 2.0)
+            y0 = h / 2.0 + r.uniform(-2.0, 2.0)
+            snr = math.exp(r.uniform(math.log(20.0), math.log(200.0)))
+            t = [x0, y0, M0, fwhm, sky]
+        mask = _blob_mask(r, h, w, x0, y0)
+        rows[kind].append((i, h, w, psf, np.array(t), snr, sky, mask))
+    out = {}
+    for kind, lst in rows.items():
+        if not lst:
+            continue
+        h = np.array([x[1] for x in lst], np.int32)
+        w = np.array([x[2] for x in lst], np.int32)
+        k = np.full(len(lst), 25, np.int32)
+        img_off = np.concatenate([[0], np.cumsum(h.astype(np.int64) * w)[:-1]]).astype(np.int64)
+        psf_off = np.arange(len(lst), dtype=np.int64) * 625
+        b = Batch("mixed", kind, h, w, img_off, k, psf_off, np.concatenate([x[3].ravel() for x in lst]),
+                  np.array([x[4] for x in lst]), np.array([x[5] for x in lst]), np.array([x[6] for x in lst]),
+                  np.array([x[0] for x in lst], np.int64), seed)
+        b.omega = np.concatenate([x[7].ravel() for x in lst])
+        out[kind] = b
+    return out

@@ -22,6 +22,18 @@ def oracle_batch(config: str, n: int, seed: int = 0, start: int = 0) -> S.Batch:
     return S.finish(b, units)
 
 
+def oracle_mixed(n: int, seed: int = 0, start: int = 0):
+    """Mixed-profile workload, one batch per model, rendered by the oracle."""
+    out = {}
+    for kind, b in S.draw_mixed(n, seed=seed, start=start).items():
+        m = from_spec(b.model)
+        ut = S.unit_truth(b)
+        units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
+                                for g in range(b.n)])
+        out[kind] = S.finish(b, units)
+    return out
+
+
 def image_parity(gpu: np.ndarray, ref: np.ndarray, rel: float = 1e-5, floor: float = 1e-6):
     """|M_gpu - M_or| <= rel * max(|M_or|, floor * max|M_or|) per pixel; returns
     (ok, worst ratio)."""
@@ -31,7 +43,8 @@ def image_parity(gpu: np.ndarray, ref: np.ndarray, rel: float = 1e-5, floor: flo
 
 
 # floors of the parameter parity metric per parameter kind (natural units)
-FLOORS = {"x0": 1.0, "y0": 1.0, "re": 0.1, "rs": 0.1, "n": 0.1, "q": 0.01, "sky": 1.0}
+FLOORS = {"x0": 1.0, "y0": 1.0, "re": 0.1, "rs": 0.1, "rout": 0.1, "rc": 0.1, "rt": 0.1, "fwhm": 0.1, "n": 0.1,
+          "q": 0.01}
 
 
 def param_parity(names, gpu, ref, sky_sigma: float = 1.0, rel: float = 1e-4):
@@ -49,7 +62,7 @@ def param_parity(names, gpu, ref, sky_sigma: float = 1.0, rel: float = 1e-4):
             r = abs(10 ** (-0.4 * (a - b)) - 1.0) / rel
         else:
             base = nm.split("_")[0]
-            fl = sky_sigma if base == "sky" else FLOORS.get(base, 0.0)
+            fl = sky_sigma if base in ("sky", "I0") else FLOORS.get(base, 0.0)
             r = abs(a - b) / (rel * max(abs(b), fl))
         worst[k] = r
         ok[k] = r <= 1.0

@@ -28,3 +28,11 @@ def single(type_: int, convolve: bool = True, fixed=None, sky: bool = False, ove
         comps.append(O.Comp(O.SKY, False, [k], []))
         k += 1
     return O.Model(comps, k, oversample=oversample)
+
+
+def to_gm(model: O.Model):
+    """The same model description for the HIP library's binding."""
+    from paper_2404_07780_amd import gmfit as G
+
+    return G.Model([G.Component(c.type, c.convolve, list(c.idx), list(c.fixed)) for c in model.comps], model.p,
+                   m0=model.m0, oversample=model.oversample, os_window=model.os_window)

@@ -249,9 +249,11 @@ def test_abi_errors():
     with pytest.raises(G.GmError) as e:
         G.gm_model_image(gm, db, b.truth)
     assert e.value.code == G.GM_EINVAL
-    bad = G.Model([G.Component(S.KING, True, [0, 1, 2, 3, 4, 5, 6], [0] * 7 + [2.0])], 7)
+    # two Sersic components with independent centres: no compiled family
+    bad = G.Model([G.Component(S.SERSIC, True, [0, 1, 2, 3, 4, 5, 6]),
+                   G.Component(S.SERSIC, True, [7, 8, 9, 10, 11, 12, 13])], 14)
     with pytest.raises(G.GmError) as e:
-        G.gm_model_image(bad, _dev_batch(b), np.zeros((2, 7)))
+        G.gm_model_image(bad, _dev_batch(b), np.zeros((2, 14)))
     assert e.value.code == G.GM_EUNSUPPORTED
     empty = G.Batch(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0),
                     np.zeros(0))

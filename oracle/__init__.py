@@ -271,6 +271,21 @@ def default_guess(model: Model, data, sigma, omega=None):
     return params, mom
 
 
+def default_guess_batch(model: Model, h, w, img_off, data, sigma, omega=None):
+    """Moment-based start vectors [n][p] and moment features [n][6] of a ragged
+    batch (one orc_default_guess call per galaxy)."""
+    n = len(h)
+    params = np.zeros((n, model.p))
+    mom = np.zeros((n, 6))
+    for g in range(n):
+        hh, ww, o = int(h[g]), int(w[g]), int(img_off[g])
+        sl = slice(o, o + hh * ww)
+        om = None if omega is None else np.asarray(omega[sl]).reshape(hh, ww)
+        params[g], mom[g] = default_guess(model, np.asarray(data[sl]).reshape(hh, ww),
+                                          np.asarray(sigma[sl]).reshape(hh, ww), om)
+    return params, mom
+
+
 def fit_batch(model: Model, h, w, img_off, data, sigma, psf_k, psf_off, psf, params0, omega=None,
               max_iter=100, lambda0=1e-3, step_tol=1e-4, nthreads=None):
     """Fit a ragged batch on `nthreads` host threads (default: all cores)."""

@@ -909,9 +909,95 @@ __device__ inline double block_sum(double v, double *sred)
     return s;
 }
 
-// Moments: sky0 = mean of usable pixels in the 2-px frame; S = usable pixels
-// with D - sky0 > 3 sigma; flux, flux-weighted centroid and central second
-// moments over S.  Start vector per family (F::default_guess).
+// Image moments of one galaxy (all threads of the workgroup call this):
+// sky0 = mean of the usable pixels in the 2-px frame; S = usable pixels with
+// D - sky0 > 3 sigma; flux, flux-weighted centroid and central second moments
+// over S; r0 = 1.1774 sqrt(lambda+), q0 = sqrt(lambda-/lambda+), theta0 =
+// atan2(2 Mxy, Mxx - Myy) / 2, m_g = m0 - 2.5 log10 max(F0, 1e-3); fewer
+// than 5 pixels in S: the cutout centre, r0 = 3, q0 = 1, theta0 = 0.
+struct Moments {
+    double sky0, f0, xc, yc, r0, q0, th0, mg, pk;
+};
+
+__device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, double m0, double *sred)
+{
+    const int tid = threadIdx.x;
+    const int H = me.h, W = me.w;
+    const int64_t npix = (int64_t)H * W;
+    double ss = 0.0, sc = 0.0;
+    for (int64_t q = tid; q < npix; q += NT) {
+        int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+        if (!(i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) continue;
+        float d;
+        if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+        ss += d;
+        sc += 1.0;
+    }
+    ss = block_sum(ss, sred);
+    sc = block_sum(sc, sred);
+    Moments mo;
+    mo.sky0 = sc > 0.0 ? ss / sc : 0.0;
+    double f0 = 0.0, fx = 0.0, fy = 0.0, cnt = 0.0, pk = 0.0;
+    for (int64_t q = tid; q < npix; q += NT) {
+        int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+        float d;
+        if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+        double dp = (double)d - mo.sky0;
+        if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
+        double x = j + 0.5, y = (double)H - i - 0.5;
+        f0 += dp; fx += dp * x; fy += dp * y; cnt += 1.0;
+        pk = fmax(pk, dp);
+    }
+    f0 = block_sum(f0, sred);
+    fx = block_sum(fx, sred);
+    fy = block_sum(fy, sred);
+    cnt = block_sum(cnt, sred);
+    {   // block max of the peak
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pk = fmax(pk, __shfl_xor(pk, o, 64));
+        __syncthreads();
+        if (lane == 0) sred[wave] = pk;
+        __syncthreads();
+        pk = sred[0];
+        for (int w = 1; w < NWAVE; ++w) pk = fmax(pk, sred[w]);
+    }
+    mo.f0 = f0;
+    mo.pk = pk > 0.0 ? pk : 1.0;
+    mo.xc = 0.5 * W; mo.yc = 0.5 * H; mo.r0 = 3.0; mo.q0 = 1.0; mo.th0 = 0.0;
+    const bool have = cnt >= 5.0 && f0 > 0.0;
+    double mxx = 0.0, myy = 0.0, mxy = 0.0;
+    if (have) {
+        mo.xc = fx / f0;
+        mo.yc = fy / f0;
+        for (int64_t q = tid; q < npix; q += NT) {
+            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+            float d;
+            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
+            double dp = (double)d - mo.sky0;
+            if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
+            double dx = j + 0.5 - mo.xc, dy = (double)H - i - 0.5 - mo.yc;
+            mxx += dp * dx * dx; myy += dp * dy * dy; mxy += dp * dx * dy;
+        }
+    }
+    mxx = block_sum(mxx, sred);
+    myy = block_sum(myy, sred);
+    mxy = block_sum(mxy, sred);
+    if (have) {
+        mxx /= f0; myy /= f0; mxy /= f0;
+        double tr = 0.5 * (mxx + myy), dd = sqrt(0.25 * (mxx - myy) * (mxx - myy) + mxy * mxy);
+        double lp = tr + dd, lm = fmax(tr - dd, 0.0);
+        mo.q0 = lp > 0.0 ? sqrt(lm / lp) : 1.0;
+        mo.q0 = fmin(fmax(mo.q0, 0.1), 1.0);
+        mo.th0 = 0.5 * atan2(2.0 * mxy, mxx - myy);
+        mo.r0 = 1.1774 * sqrt(fmax(lp, 0.0));
+        mo.r0 = fmin(fmax(mo.r0, 1.0), 0.25 * W);
+    }
+    mo.mg = m0 - 2.5 * log10(fmax(f0, 1e-3));
+    return mo;
+}
+
+// Start vector per family (F::default_guess) from the image moments.
 template <class F>
 __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, GuessArgs ga)
 {
@@ -919,86 +1005,18 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
     const int tid = threadIdx.x;
     for (int g = blockIdx.x; g < ga.n_gal; g += gridDim.x) {
         const Meta me = ba.meta[g];
-        const int H = me.h, W = me.w;
-        const int64_t npix = (int64_t)H * W;
-        double ss = 0.0, sc = 0.0;
-        for (int64_t q = tid; q < npix; q += NT) {
-            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
-            if (!(i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) continue;
-            float d;
-            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-            ss += d;
-            sc += 1.0;
-        }
-        ss = block_sum(ss, sred);
-        sc = block_sum(sc, sred);
-        const double sky0 = sc > 0.0 ? ss / sc : 0.0;
-        double f0 = 0.0, fx = 0.0, fy = 0.0, cnt = 0.0, pk = 0.0;
-        for (int64_t q = tid; q < npix; q += NT) {
-            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
-            float d;
-            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-            double dp = (double)d - sky0;
-            if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
-            double x = j + 0.5, y = (double)H - i - 0.5;
-            f0 += dp; fx += dp * x; fy += dp * y; cnt += 1.0;
-            pk = fmax(pk, dp);
-        }
-        f0 = block_sum(f0, sred);
-        fx = block_sum(fx, sred);
-        fy = block_sum(fy, sred);
-        cnt = block_sum(cnt, sred);
-        {   // block max of the peak
-            const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) pk = fmax(pk, __shfl_xor(pk, o, 64));
-            __syncthreads();
-            if (lane == 0) sred[wave] = pk;
-            __syncthreads();
-            pk = sred[0];
-            for (int w = 1; w < NWAVE; ++w) pk = fmax(pk, sred[w]);
-        }
-        double xc = 0.5 * W, yc = 0.5 * H, r0 = 3.0, q0 = 1.0, th0 = 0.0;
-        const bool have = cnt >= 5.0 && f0 > 0.0;
-        double mxx = 0.0, myy = 0.0, mxy = 0.0;
-        if (have) {
-            xc = fx / f0;
-            yc = fy / f0;
-            for (int64_t q = tid; q < npix; q += NT) {
-                int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
-                float d;
-                if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-                double dp = (double)d - sky0;
-                if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
-                double dx = j + 0.5 - xc, dy = (double)H - i - 0.5 - yc;
-                mxx += dp * dx * dx; myy += dp * dy * dy; mxy += dp * dx * dy;
-            }
-        }
-        mxx = block_sum(mxx, sred);
-        myy = block_sum(myy, sred);
-        mxy = block_sum(mxy, sred);
+        const Moments mo = image_moments(ba, me, ma.m0, sred);
         if (tid == 0) {
-            if (have) {
-                mxx /= f0; myy /= f0; mxy /= f0;
-                double tr = 0.5 * (mxx + myy), dd = sqrt(0.25 * (mxx - myy) * (mxx - myy) + mxy * mxy);
-                double lp = tr + dd, lm = fmax(tr - dd, 0.0);
-                q0 = lp > 0.0 ? sqrt(lm / lp) : 1.0;
-                q0 = fmin(fmax(q0, 0.1), 1.0);
-                th0 = 0.5 * atan2(2.0 * mxy, mxx - myy);
-                r0 = 1.1774 * sqrt(fmax(lp, 0.0));
-                r0 = fmin(fmax(r0, 1.0), 0.25 * W);
-            }
-            double mg = ma.m0 - 2.5 * log10(fmax(f0, 1e-3));
-            double pa0 = th0 * 180.0 / kPi;
+            double pa0 = mo.th0 * 180.0 / kPi;
             if (pa0 < 0.0) pa0 += 180.0;
             if (ga.moments) {
-                double *mo = ga.moments + (int64_t)g * 6;
-                mo[0] = xc - 0.5 * W; mo[1] = yc - 0.5 * H; mo[2] = mg;
-                mo[3] = log(r0); mo[4] = q0; mo[5] = th0;
+                double *m6 = ga.moments + (int64_t)g * 6;
+                m6[0] = mo.xc - 0.5 * me.w; m6[1] = mo.yc - 0.5 * me.h; m6[2] = mo.mg;
+                m6[3] = log(mo.r0); m6[4] = mo.q0; m6[5] = mo.th0;
             }
             double nat[F::P];
-            const double ms = mg + 2.5 * log10((double)(ma.nflux > 1 ? ma.nflux : 1));
-            F::default_guess(xc, yc, ms, r0, q0, pa0, sky0, pk > 0.0 ? pk : 1.0, nat);
+            const double ms = mo.mg + 2.5 * log10((double)(ma.nflux > 1 ? ma.nflux : 1));
+            F::default_guess(mo.xc, mo.yc, ms, mo.r0, mo.q0, pa0, mo.sky0, mo.pk, nat);
             double *out = ga.params + (int64_t)g * ma.p;
             for (int k = 0; k < F::P; ++k)
                 if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];

@@ -118,9 +118,9 @@ def test_mixed_fit(mixed, kind):
     gmod = to_gm(om)
     db = _dev(b)
     start, _ = G.gm_default_guess(gmod, db)
-    start = start.cpu().numpy()
     gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gmod, db, start)]
-    rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, start,
+    ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, omega=b.omega)
+    rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
                                  omega=b.omega)
     names = S.MODEL_SPECS[b.model]["names"]
     both = (gs == 0) & (rs == 0)

@@ -133,6 +133,8 @@ def lib():
         L.orc_fit.argtypes = [p, i, i, p, p, p, p, i, p, p, p, p, p]
         L.orc_param_errors.argtypes = [p, i, i, p, p, p, p, i, p, p, p]
         L.orc_default_guess.argtypes = [p, i, i, p, p, p, p, p]
+        L.orc_moments.argtypes = [i, i, p, p, p, d, p]
+        L.orc_moments.restype = None
         L.orc_fit_batch.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p, p, p, p, i]
         _lib = L
     return _lib
@@ -254,6 +256,16 @@ def param_errors(model: Model, data, sigma, psf, params, omega=None, want_cov=Fa
     lib().orc_param_errors(C.byref(mc), data.shape[0], data.shape[1], _ptr(data), _ptr(sigma), _ptr(om),
                            _ptr(psf), psf.shape[0], _ptr(params), _ptr(err), _ptr(cov))
     return (err, cov) if want_cov else err
+
+
+def moments(data, sigma, omega=None, m0: float = 22.5):
+    """Image moments {sky0, F0, xc, yc, m_g, r0, q0, th0 (rad), peak}."""
+    data = _f32(data)
+    sigma = _f32(sigma)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.uint8)
+    out = np.zeros(9)
+    lib().orc_moments(data.shape[0], data.shape[1], _ptr(data), _ptr(sigma), _ptr(om), float(m0), _ptr(out))
+    return out
 
 
 def default_guess(model: Model, data, sigma, omega=None):

@@ -975,26 +975,20 @@ int orc_param_errors(const orc_model *m, int h, int w, const float *data, const 
 /* Default initial guess from image moments                                 */
 /* ------------------------------------------------------------------------ */
 
-/* The paper takes start values from SExtractor (Sec. 3, Appendix A); this
- * build derives them from image moments instead:
- *  1. sky0 = mean of the usable pixels in the 2-px outer frame;
- *  2. S = usable pixels with D - sky0 > 3 sigma;
- *  3. F0 = sum_S (D - sky0); flux-weighted centroid and central second
- *     moments over S; lambda+- their eigenvalues;
- *  4. q0 = clamp(sqrt(lambda-/lambda+), 0.1, 1),
- *     theta0 = atan2(2 Mxy, Mxx - Myy) / 2, r0 = clamp(1.1774 sqrt(lambda+), 1, W/4),
- *     m_g = m0 - 2.5 log10 max(F0, 1e-3);
- *  5. fewer than 5 pixels in S: centre of the cutout, r0 = 3, q0 = 1, theta0 = 0.
- * mom (nullable) receives {x_c - W/2, y_c - H/2, m_g, ln r0, q0, theta0}.
- * Per component (flux split evenly over the components that carry a
- * magnitude or amplitude): Sersic n = 2 alone, n = 4 and r_e = r0/2 with
- * another radial component; exponential disk r_s = r0 / 1.678347; Ferrer
- * r_out = r0; King r_c = r0/2, r_t = 4 r0, I0 = peak; Gaussian FWHM = r0,
- * I0 = peak; Moffat FWHM = r0; q and PA from the moments where free. */
-int orc_default_guess(const orc_model *m, int h, int w, const float *data, const float *sigma,
-                      const uint8_t *omega, double *params, double *mom)
+/* Image moments (the source-extraction step the paper delegates to an
+ * external detector, replaced here by plain moments):
+ *   sky0 = mean of the usable pixels in the 2-px outer frame;
+ *   S = usable pixels with D - sky0 > 3 sigma;
+ *   F0 = sum over S of D - sky0; (xc, yc) its flux-weighted centroid;
+ *   central second moments over S, eigenvalues l+ >= l-;
+ *   q0 = clamp(sqrt(l-/l+), 0.1, 1), th0 = atan2(2 Mxy, Mxx - Myy) / 2 (rad),
+ *   r0 = clamp(1.1774 sqrt(l+), 1, W/4), m_g = m0 - 2.5 log10 max(F0, 1e-3);
+ *   fewer than 5 pixels in S (or F0 <= 0): cutout centre, r0 = 3, q0 = 1,
+ *   th0 = 0; peak = max over S of D - sky0 (1 when S is empty).
+ * out[9] = {sky0, F0, xc, yc, m_g, r0, q0, th0, peak}. */
+void orc_moments(int h, int w, const float *data, const float *sigma, const uint8_t *omega, double m0,
+                 double *out)
 {
-    if (orc_validate(m)) return ORC_EINVAL;
     /* 1. border sky */
     double ssum = 0.0; long scount = 0;
     for (int i = 0; i < h; ++i)
@@ -1044,7 +1038,35 @@ int orc_default_guess(const orc_model *m, int h, int w, const float *data, const
         if (r0 < 1.0) r0 = 1.0;
         if (r0 > 0.25 * w) r0 = 0.25 * w;
     }
-    double mg = m->m0 - 2.5 * log10(F0 > 1e-3 ? F0 : 1e-3);
+    out[0] = sky0; out[1] = F0; out[2] = xc; out[3] = yc;
+    out[4] = m0 - 2.5 * log10(F0 > 1e-3 ? F0 : 1e-3);
+    out[5] = r0; out[6] = q0; out[7] = th0; out[8] = peak > 0.0 ? peak : 1.0;
+}
+
+/* The paper takes start values from SExtractor (Sec. 3, Appendix A); this
+ * build derives them from image moments instead:
+ *  1. sky0 = mean of the usable pixels in the 2-px outer frame;
+ *  2. S = usable pixels with D - sky0 > 3 sigma;
+ *  3. F0 = sum_S (D - sky0); flux-weighted centroid and central second
+ *     moments over S; lambda+- their eigenvalues;
+ *  4. q0 = clamp(sqrt(lambda-/lambda+), 0.1, 1),
+ *     theta0 = atan2(2 Mxy, Mxx - Myy) / 2, r0 = clamp(1.1774 sqrt(lambda+), 1, W/4),
+ *     m_g = m0 - 2.5 log10 max(F0, 1e-3);
+ *  5. fewer than 5 pixels in S: centre of the cutout, r0 = 3, q0 = 1, theta0 = 0.
+ * mom (nullable) receives {x_c - W/2, y_c - H/2, m_g, ln r0, q0, theta0}.
+ * Per component (flux split evenly over the components that carry a
+ * magnitude or amplitude): Sersic n = 2 alone, n = 4 and r_e = r0/2 with
+ * another radial component; exponential disk r_s = r0 / 1.678347; Ferrer
+ * r_out = r0; King r_c = r0/2, r_t = 4 r0, I0 = peak; Gaussian FWHM = r0,
+ * I0 = peak; Moffat FWHM = r0; q and PA from the moments where free. */
+int orc_default_guess(const orc_model *m, int h, int w, const float *data, const float *sigma,
+                      const uint8_t *omega, double *params, double *mom)
+{
+    if (orc_validate(m)) return ORC_EINVAL;
+    double mo[9];
+    orc_moments(h, w, data, sigma, omega, m->m0, mo);
+    const double sky0 = mo[0], xc = mo[2], yc = mo[3], mg = mo[4], r0 = mo[5], q0 = mo[6], th0 = mo[7];
+    const double peak = mo[8];
     double pa0 = th0 * 180.0 / ORC_PI;
     if (pa0 < 0.0) pa0 += 180.0;
     if (mom) {

@@ -67,6 +67,8 @@ int orc_fit(const orc_model *m, int h, int w, const float *data, const float *si
 int orc_param_errors(const orc_model *m, int h, int w, const float *data, const float *sigma,
                      const uint8_t *omega, const float *psf, int k, const double *params,
                      double *err, double *cov);
+void orc_moments(int h, int w, const float *data, const float *sigma, const uint8_t *omega, double m0,
+                 double *out);
 int orc_default_guess(const orc_model *m, int h, int w, const float *data, const float *sigma,
                       const uint8_t *omega, double *params, double *mom);
 int orc_fit_batch(const orc_model *m, int n_gal, const int32_t *h, const int32_t *w,

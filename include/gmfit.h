@@ -96,6 +96,8 @@ typedef struct {
     int32_t max_iter;         /* trials per galaxy (100) */
     double lambda0;           /* initial damping (1e-3) */
     double step_tol;          /* stop when max_k |GN step_k| / sigma_k < step_tol (1e-4) */
+    const int32_t *active;    /* DEVICE [n_gal] or NULL: galaxies with active[g] == 0 are
+                                 skipped and their outputs left untouched */
 } gm_fit_opts;
 
 typedef struct gm_ctx gm_ctx;
@@ -142,6 +144,119 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
  * A galaxy whose J^T W J is not positive definite gets NaN errors. */
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                     const double *params, double *err_out, double *cov_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal.  The paper motivates learned parameter estimators
+ * (Sec. 1) and names the hand-chosen initial parameters as a limitation of
+ * its fitter (Sec. 7); it fixes no network, so what follows is this
+ * library's design.
+ *
+ * Features (1056 per galaxy, BF16): with the image moments of
+ * gm_default_guess (sky0, F0, centroid x_c y_c, m_g, r0, q0, theta0) and
+ * F0' = max(F0, 1), 1024 area-weighted cells -- cell (a, b) covers rows
+ * [a H/32, (a+1) H/32) and columns [b W/32, (b+1) W/32); its value is the mean
+ * of D - sky0 over its usable area times the cell area H W / 1024, scaled by
+ * 32 / F0' (0 if nothing is usable) -- then (x_c - W/2)/2, (y_c - H/2)/2,
+ * (m_g - 14)/2, ln r0 - 1.5, e0 cos 2 theta0, e0 sin 2 theta0 with
+ * e0 = (1 - q0)/(1 + q0), then 26 zeros.
+ *
+ * Targets (the first 7 outputs; the rest are 0) of a single Sersic + sky:
+ * x0 - x_c, y0 - y_c, (mag - m_g)/0.5, (ln re - 1.7)/0.6, (ln n - 0.6)/0.6,
+ * e cos 2 pa / 0.3, e sin 2 pa / 0.3 with e = (1 - q)/(1 + q).  Decoding
+ * inverts them with e capped at 0.9 and sky = sky0; a proposal is valid when
+ * finite and inside the LM bounds (0 <= x0 <= W, 0 <= y0 <= H,
+ * 0.1 <= re <= 2 max(H, W), 0.2 <= n <= 10).
+ *
+ * Network: n_hidden layers of `hidden` units with the exact-erf GELU, then a
+ * linear layer of out_dim outputs of which the first n_out enter the loss.
+ * Parameters are one flat FP32 vector, layer by layer W_l [out][in]
+ * (row-major) then b_l [out]; products use the BF16 copy of the weights, BF16
+ * activations and FP32 accumulation.  Loss: the mean over rows and the n_out
+ * used outputs of the squared error.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t in_dim;           /* 1056 for the proposal; multiples of 8 throughout */
+    int32_t hidden;           /* 512 */
+    int32_t n_hidden;         /* 3 (1..16) */
+    int32_t out_dim;          /* 16 */
+    int32_t n_out;            /* 7 outputs enter the loss and the decoding */
+    float *params;            /* DEVICE FP32 master parameters (gm_mlp_param_count) */
+    uint16_t *params_bf16;    /* DEVICE BF16 copy, same layout, 16-byte aligned */
+    float *grad;              /* DEVICE gradient, same layout (training only) */
+    float *adam_m, *adam_v;   /* DEVICE AdamW moments, same layout (training only) */
+} gm_mlp;
+
+typedef struct {
+    double lr, beta1, beta2, eps, weight_decay;
+} gm_adamw;
+
+/* Number of parameters of the network's sizes, -1 if they are invalid. */
+int64_t gm_mlp_param_count(const gm_mlp *mlp);
+
+/* params_bf16 <- BF16(params), round to nearest even. */
+int gm_mlp_sync(gm_ctx *ctx, const gm_mlp *mlp, void *stream);
+
+/* out [n][out_dim] (device FP32) for x [n][ldx] (device BF16, ldx >= in_dim,
+ * a multiple of 8, 16-byte aligned). */
+int gm_mlp_forward(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t *x, int64_t ldx,
+                   float *out, void *stream);
+
+/* Gradient of the loss over rows[0..n) of x and targets (device; rows NULL =
+ * the first n rows, else every entry must index a row of both x and targets;
+ * targets [.][out_dim] FP32) into mlp->grad; loss_out (device FP64, nullable)
+ * receives the loss. */
+int gm_mlp_backward(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t *x, int64_t ldx,
+                    const int32_t *rows, const float *targets, double *loss_out, void *stream);
+
+/* One AdamW step (Loshchilov and Hutter: decoupled weight decay, bias-corrected
+ * moments; step counts from 1) from mlp->grad; refreshes params_bf16. */
+int gm_mlp_adamw(gm_ctx *ctx, const gm_mlp *mlp, int64_t step, const gm_adamw *opt, void *stream);
+
+/* gm_mlp_backward then gm_mlp_adamw. */
+int gm_mlp_train_step(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t *x, int64_t ldx,
+                      const int32_t *rows, const float *targets, int64_t step, const gm_adamw *opt,
+                      double *loss_out, void *stream);
+
+/* Features of every galaxy: x_out [n_gal][ldx] BF16 (device, ldx >= 1056, a
+ * multiple of 8); moments_out (device, nullable) [n_gal][8] =
+ * {sky0, F0, x_c, y_c, m_g, r0, q0, theta0_rad}.  Any model (m0 is used). */
+int gm_features(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, uint16_t *x_out,
+                int64_t ldx, double *moments_out, void *stream);
+
+/* Targets [n_gal][out_dim] (device FP32) of the truths (device [n_gal][p]) of
+ * a single-Sersic + sky model whose 8 slots are all columns (else
+ * GM_EUNSUPPORTED); moments from gm_features. */
+int gm_proposal_targets(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
+                        const double *truth, const double *moments, float *targets_out,
+                        int32_t out_dim, void *stream);
+
+/* Decode network outputs [n_gal][out_dim] into start vectors params_out
+ * [n_gal][p] and valid_out [n_gal] (1 = usable), same model restriction. */
+int gm_proposal_decode(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
+                       const float *out, int32_t out_dim, const double *moments,
+                       double *params_out, int32_t *valid_out, void *stream);
+
+/* LM from the network's proposal with the moment-based guess as fallback:
+ * galaxies whose proposal is invalid, or whose LM from it does not end
+ * GM_ST_CONVERGED, are refitted from gm_default_guess; their reported result
+ * is the refit and niter_out counts the trials of both fits.  fallback_out
+ * (device, nullable) [n_gal] = 1 where the fallback ran.  opts->active is
+ * ignored.  Same model restriction as gm_proposal_decode. */
+int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
+                   const gm_fit_opts *opts, double *params_out, double *chi2_out,
+                   int32_t *niter_out, int32_t *status_out, int32_t *fallback_out, void *stream);
+
+/* Training images: data_out = F unit + sky + sigma z per galaxy, with unit a
+ * noiseless unit-flux model image (device FP32 at img_off, host sizes),
+ * F = snr sigma / max(unit) so that snr is the peak signal-to-noise ratio,
+ * and z standard normal from Philox4x32-10 (Salmon et al. 2011) keyed by
+ * seed, counter {pixel/4, first_index + g (64 bit), 0}, Box-Muller on word
+ * pairs.  sigma_out (nullable) is filled with sigma; mag_out (nullable)
+ * [g * mag_stride] = m0 - 2.5 log10 F.  snr, sky: device [n_gal] FP64. */
+int gm_synth_noise(gm_ctx *ctx, int32_t n_gal, const int32_t *h, const int32_t *w,
+                   const int64_t *img_off, const float *unit, const double *snr, const double *sky,
+                   float sigma, double m0, uint64_t seed, int64_t first_index, float *data_out,
+                   float *sigma_out, double *mag_out, int32_t mag_stride, void *stream);
 
 #ifdef __cplusplus
 }

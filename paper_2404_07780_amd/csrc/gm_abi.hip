@@ -131,11 +131,6 @@ bool comp_ok(const gm_component &c, int p)
     return true;
 }
 
-struct Match {
-    FamilyOps ops{};
-    CallInfo ci{};
-};
-
 // internal index k <- slot s of component c
 void take(const gm_component &c, int s, int k, ModelArgs &ma)
 {
@@ -154,6 +149,10 @@ FamilyOps single_ops(int type)
     default: return ops_moffat();
     }
 }
+
+}  // namespace
+
+namespace gm {
 
 int match_model(const gm_model *m, Match &out)
 {
@@ -236,6 +235,8 @@ int match_model(const gm_model *m, Match &out)
     out.ops = ops;
     out.ci.ma = ma;
     out.ci.convolved = convolved;
+    out.single_type = nrad == 1 ? rad[0]->type : 0;
+    out.has_sky = sky != nullptr;
     return GM_OK;
 }
 
@@ -263,20 +264,7 @@ int prologue(gm_ctx *c, const gm_model *m, const gm_batch *b, Match &mt)
     return GM_OK;
 }
 
-struct Scoped {
-    int prev = -1;
-    explicit Scoped(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~Scoped()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-}  // namespace
+}  // namespace gm
 
 extern "C" {
 
@@ -315,6 +303,7 @@ void gm_destroy(gm_ctx *c)
     if (c->dev) (void)hipFree(c->dev);
     if (c->host) (void)hipHostFree(c->host);
     if (c->unit_psf) (void)hipFree(c->unit_psf);
+    if (c->mlp_ws) (void)hipFree(c->mlp_ws);
     if (c->staged) (void)hipEventDestroy(c->staged);
     delete c;
 }

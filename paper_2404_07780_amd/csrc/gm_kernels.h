@@ -588,6 +588,7 @@ struct LMShared {
 
 struct FitArgs {
     const int *order;
+    const int *active;        // nullable: galaxies with active[g] == 0 are skipped
     int n_gal;
     int *queue;
     double *params, *chi2;
@@ -717,6 +718,10 @@ __global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, 
         const int qi = uniform(s.gal);
         if (qi >= fa.n_gal) break;
         const int g = uniform(fa.order[qi]);
+        if (fa.active && uniform(fa.active[g]) == 0) {
+            __syncthreads();      // s.gal is rewritten by thread 0 next
+            continue;
+        }
         const Meta me = ba.meta[g];
         if (tid == 0) {
             double *tmp = reinterpret_cast<double *>(planes);

@@ -22,6 +22,8 @@ struct gm_ctx {
     hipEvent_t staged = nullptr;  // last copy out of the staging buffer
     bool pending = false;
     float *unit_psf = nullptr;    // device 1x1 kernel {1.0}: runs unconvolved models
+    void *mlp_ws = nullptr;       // grow-only device workspace of the learned proposal
+    size_t mlp_ws_bytes = 0;
 };
 
 namespace gm {
@@ -175,6 +177,7 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
     FitArgs fa{};
     fa.order = reinterpret_cast<const int *>(sg.extra);
+    fa.active = o ? o->active : nullptr;
     fa.n_gal = b->n_gal;
     fa.queue = sg.queue;
     fa.params = params;
@@ -254,5 +257,31 @@ FamilyOps ops_ferrer();
 FamilyOps ops_king();
 FamilyOps ops_gaussian();
 FamilyOps ops_moffat();
+
+// A caller's gm_model matched against the compiled families (gm_abi.hip).
+struct Match {
+    FamilyOps ops{};
+    CallInfo ci{};
+    int single_type = 0;      // profile type of a one-component model, else 0
+    bool has_sky = false;
+};
+int match_model(const gm_model *m, Match &out);
+int check_batch(const gm_batch *b, bool convolved);
+// validate context, model and batch; fills mt (mt.ci.b = b)
+int prologue(gm_ctx *c, const gm_model *m, const gm_batch *b, Match &mt);
+
+// makes the context's device current for the scope of a call
+struct Scoped {
+    int prev = -1;
+    explicit Scoped(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~Scoped()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 }  // namespace gm

@@ -24,7 +24,9 @@ SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
 
 # exported symbols (one per declaration of include/gmfit.h)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",
-           "gm_default_guess", "gm_fit_batch", "gm_param_errors")
+           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_mlp_param_count", "gm_mlp_sync",
+           "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
+           "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise")
 
 
 class GmError(RuntimeError):
@@ -50,7 +52,19 @@ class gm_batch(C.Structure):
 
 
 class gm_fit_opts(C.Structure):
-    _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double)]
+    _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double),
+                ("active", C.c_void_p)]
+
+
+class gm_mlp(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32), ("out_dim", C.c_int32),
+                ("n_out", C.c_int32), ("params", C.c_void_p), ("params_bf16", C.c_void_p), ("grad", C.c_void_p),
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
+
+
+class gm_adamw(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double)]
 
 
 _lib = None
@@ -75,7 +89,23 @@ def lib() -> C.CDLL:
         L.gm_default_guess.argtypes = [v, p, p, v, v, v]
         L.gm_fit_batch.argtypes = [v, p, p, p, v, v, v, v, v]
         L.gm_param_errors.argtypes = [v, p, p, v, v, v, v]
-        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors"):
+        i64, u64, f, d = C.c_int64, C.c_uint64, C.c_float, C.c_double
+        L.gm_mlp_param_count.argtypes = [p]
+        L.gm_mlp_param_count.restype = i64
+        L.gm_mlp_sync.argtypes = [v, p, v]
+        L.gm_mlp_forward.argtypes = [v, p, i, v, i64, v, v]
+        L.gm_mlp_backward.argtypes = [v, p, i, v, i64, v, v, v, v]
+        L.gm_mlp_adamw.argtypes = [v, p, i64, p, v]
+        L.gm_mlp_train_step.argtypes = [v, p, i, v, i64, v, v, i64, p, v, v]
+        L.gm_features.argtypes = [v, p, p, v, i64, v, v]
+        L.gm_proposal_targets.argtypes = [v, p, p, v, v, v, i, v]
+        L.gm_proposal_decode.argtypes = [v, p, p, v, i, v, v, v, v]
+        L.gm_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v]
+        L.gm_synth_noise.argtypes = [v, i, v, v, v, v, v, v, f, d, u64, i64, v, v, v, i, v]
+        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
+                     "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
+                     "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
+                     "gm_synth_noise"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -255,10 +285,11 @@ def gm_default_guess(model: Model, batch: Batch, ctx: Optional[Context] = None):
 
 
 def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambda0: float = 1e-3,
-                 step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None):
+                 step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None, active=None):
     """Returns (params, chi2, niter, status) as device tensors.  `out` may pass
     preallocated (params, chi2, niter, status); params is then overwritten with
-    params0 first unless params0 is None."""
+    params0 first unless params0 is None.  `active` (device int32 [n]) skips
+    the galaxies where it is 0."""
     ctx = ctx or context(batch.device.index)
     if out is None:
         params = _params_dev(params0, batch, model.p).clone()
@@ -269,7 +300,7 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
         params, chi2, niter, status = out
         if params0 is not None:
             params.copy_(_params_dev(params0, batch, model.p))
-    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol))
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr())
     m, b = model.c(), batch.c()
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
@@ -285,3 +316,174 @@ def gm_param_errors(model: Model, batch: Batch, params, want_cov: bool = False, 
     _check("gm_param_errors",
            lib().gm_param_errors(ctx.handle, C.byref(m), C.byref(b), _ptr(pr), _ptr(err), _ptr(cov), _stream()))
     return (err, cov) if want_cov else err
+
+
+# ---------------------------------------------------------------- learned proposal
+class MLP:
+    """Network parameters on the device: FP32 master, BF16 copy, gradient and
+    AdamW moments (flat vectors, layout of include/gmfit.h)."""
+
+    def __init__(self, params, in_dim: int = 1056, hidden: int = 512, n_hidden: int = 3, out_dim: int = 16,
+                 n_out: int = 7, device=None, train: bool = True):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.dims = (in_dim, hidden, n_hidden, out_dim, n_out)
+        self.device = dev
+        probe = gm_mlp(in_dim, hidden, n_hidden, out_dim, n_out)
+        cnt = lib().gm_mlp_param_count(C.byref(probe))
+        if cnt < 0:
+            raise ValueError("invalid network sizes")
+        t = params if isinstance(params, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(params, np.float32))
+        if t.numel() != cnt:
+            raise ValueError(f"expected {cnt} parameters, got {t.numel()}")
+        self.params = t.to(device=dev, dtype=torch.float32).contiguous().clone()
+        self.params_bf16 = torch.empty(cnt, dtype=torch.bfloat16, device=dev)
+        self.grad = torch.zeros(cnt, dtype=torch.float32, device=dev) if train else None
+        self.adam_m = torch.zeros(cnt, dtype=torch.float32, device=dev) if train else None
+        self.adam_v = torch.zeros(cnt, dtype=torch.float32, device=dev) if train else None
+        self.step = 0
+        gm_mlp_sync(self)
+
+    def c(self) -> gm_mlp:
+        m = gm_mlp(*self.dims)
+        m.params = self.params.data_ptr()
+        m.params_bf16 = self.params_bf16.data_ptr()
+        for name in ("grad", "adam_m", "adam_v"):
+            t = getattr(self, name)
+            setattr(m, name, None if t is None else t.data_ptr())
+        return m
+
+
+def _ctx_for(device, ctx):
+    return ctx or context(device.index)
+
+
+def _bf16_rows(x: torch.Tensor, min_cols: int) -> torch.Tensor:
+    if x.dtype != torch.bfloat16 or x.dim() != 2 or x.shape[1] < min_cols or x.stride(1) != 1:
+        raise ValueError("x must be a 2-D BF16 tensor with unit column stride")
+    return x
+
+
+def gm_mlp_sync(mlp: MLP, ctx: Optional[Context] = None) -> None:
+    ctx = _ctx_for(mlp.device, ctx)
+    m = mlp.c()
+    _check("gm_mlp_sync", lib().gm_mlp_sync(ctx.handle, C.byref(m), _stream()))
+
+
+def gm_mlp_forward(mlp: MLP, x: torch.Tensor, ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = _ctx_for(mlp.device, ctx)
+    x = _bf16_rows(x, mlp.dims[0])
+    out = torch.empty(x.shape[0], mlp.dims[3], dtype=torch.float32, device=mlp.device)
+    m = mlp.c()
+    _check("gm_mlp_forward", lib().gm_mlp_forward(ctx.handle, C.byref(m), x.shape[0], _ptr(x), x.stride(0),
+                                                  _ptr(out), _stream()))
+    return out
+
+
+def gm_mlp_backward(mlp: MLP, x: torch.Tensor, targets: torch.Tensor, rows: Optional[torch.Tensor] = None,
+                    n: Optional[int] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """Gradient into mlp.grad; returns the loss (device FP64 scalar)."""
+    ctx = _ctx_for(mlp.device, ctx)
+    x = _bf16_rows(x, mlp.dims[0])
+    n = int(rows.numel() if rows is not None else (x.shape[0] if n is None else n))
+    loss = torch.empty((), dtype=torch.float64, device=mlp.device)
+    m = mlp.c()
+    _check("gm_mlp_backward", lib().gm_mlp_backward(ctx.handle, C.byref(m), n, _ptr(x), x.stride(0), _ptr(rows),
+                                                    _ptr(targets), _ptr(loss), _stream()))
+    return loss
+
+
+def gm_mlp_adamw(mlp: MLP, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                 weight_decay: float = 0.0, ctx: Optional[Context] = None) -> None:
+    ctx = _ctx_for(mlp.device, ctx)
+    mlp.step += 1
+    o = gm_adamw(lr, beta1, beta2, eps, weight_decay)
+    m = mlp.c()
+    _check("gm_mlp_adamw", lib().gm_mlp_adamw(ctx.handle, C.byref(m), mlp.step, C.byref(o), _stream()))
+
+
+def gm_mlp_train_step(mlp: MLP, x: torch.Tensor, targets: torch.Tensor, rows: Optional[torch.Tensor], lr: float,
+                      beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, weight_decay: float = 0.0,
+                      loss: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = _ctx_for(mlp.device, ctx)
+    x = _bf16_rows(x, mlp.dims[0])
+    n = int(rows.numel() if rows is not None else x.shape[0])
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=mlp.device)
+    mlp.step += 1
+    o = gm_adamw(lr, beta1, beta2, eps, weight_decay)
+    m = mlp.c()
+    _check("gm_mlp_train_step", lib().gm_mlp_train_step(ctx.handle, C.byref(m), n, _ptr(x), x.stride(0),
+                                                        _ptr(rows), _ptr(targets), mlp.step, C.byref(o),
+                                                        _ptr(loss), _stream()))
+    return loss
+
+
+def gm_features(model: Model, batch: Batch, ctx: Optional[Context] = None, ldx: int = 1056):
+    """(features [n][ldx] BF16, moments [n][8] FP64) as device tensors."""
+    ctx = _ctx_for(batch.device, ctx)
+    x = torch.zeros(batch.n, ldx, dtype=torch.bfloat16, device=batch.device)
+    mom = torch.empty(batch.n, 8, dtype=torch.float64, device=batch.device)
+    m, b = model.c(), batch.c()
+    _check("gm_features", lib().gm_features(ctx.handle, C.byref(m), C.byref(b), _ptr(x), ldx, _ptr(mom), _stream()))
+    return x, mom
+
+
+def gm_proposal_targets(model: Model, batch: Batch, truth, moments: torch.Tensor, out_dim: int = 16,
+                        ctx: Optional[Context] = None) -> torch.Tensor:
+    ctx = _ctx_for(batch.device, ctx)
+    tr = _params_dev(truth, batch, model.p)
+    t = torch.empty(batch.n, out_dim, dtype=torch.float32, device=batch.device)
+    m, b = model.c(), batch.c()
+    _check("gm_proposal_targets", lib().gm_proposal_targets(ctx.handle, C.byref(m), C.byref(b), _ptr(tr),
+                                                            _ptr(moments), _ptr(t), out_dim, _stream()))
+    return t
+
+
+def gm_proposal_decode(model: Model, batch: Batch, out: torch.Tensor, moments: torch.Tensor,
+                       ctx: Optional[Context] = None):
+    ctx = _ctx_for(batch.device, ctx)
+    params = torch.zeros(batch.n, model.p, dtype=torch.float64, device=batch.device)
+    valid = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
+    m, b = model.c(), batch.c()
+    _check("gm_proposal_decode", lib().gm_proposal_decode(ctx.handle, C.byref(m), C.byref(b), _ptr(out),
+                                                          out.shape[1], _ptr(moments), _ptr(params), _ptr(valid),
+                                                          _stream()))
+    return params, valid
+
+
+def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, lambda0: float = 1e-3,
+                   step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None):
+    """(params, chi2, niter, status, fallback) as device tensors."""
+    ctx = _ctx_for(batch.device, ctx)
+    if out is None:
+        params = torch.zeros(batch.n, model.p, dtype=torch.float64, device=batch.device)
+        chi2 = torch.empty(batch.n, dtype=torch.float64, device=batch.device)
+        niter = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
+        status = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
+        fallback = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
+    else:
+        params, chi2, niter, status, fallback = out
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None)
+    m, b, ml = model.c(), batch.c(), mlp.c()
+    _check("gm_fit_learned", lib().gm_fit_learned(ctx.handle, C.byref(m), C.byref(b), C.byref(ml), C.byref(o),
+                                                  _ptr(params), _ptr(chi2), _ptr(niter), _ptr(status),
+                                                  _ptr(fallback), _stream()))
+    return params, chi2, niter, status, fallback
+
+
+def gm_synth_noise(h, w, img_off, unit: torch.Tensor, snr: torch.Tensor, sky: torch.Tensor, sigma: float,
+                   seed: int, first_index: int = 0, m0: float = 22.5, mag_out: Optional[torch.Tensor] = None,
+                   mag_stride: int = 1, ctx: Optional[Context] = None):
+    """(data, sigma map) device FP32 images; mag_out[g * mag_stride] gets the
+    magnitude that gives each galaxy its peak SNR."""
+    ctx = _ctx_for(unit.device, ctx)
+    h = np.ascontiguousarray(h, np.int32)
+    w = np.ascontiguousarray(w, np.int32)
+    img_off = np.ascontiguousarray(img_off, np.int64)
+    data = torch.empty_like(unit)
+    sig = torch.empty_like(unit)
+    _check("gm_synth_noise", lib().gm_synth_noise(ctx.handle, len(h), h.ctypes.data, w.ctypes.data,
+                                                  img_off.ctypes.data, _ptr(unit), _ptr(snr), _ptr(sky),
+                                                  float(sigma), float(m0), int(seed), int(first_index), _ptr(data),
+                                                  _ptr(sig), _ptr(mag_out), int(mag_stride), _stream()))
+    return data, sig

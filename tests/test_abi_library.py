@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2404_07780_amd", "lib", "libgmfit.so")
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(gm_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|void|const char \*)\s*\**\s*(gm_\w+)\s*\(", src, flags=re.M)))
 
 
 @pytest.fixture(scope="module")

@@ -1,25 +1,29 @@
 """Benchmark: galaxies fitted per second by batched Levenberg-Marquardt on one
-MI355X.
+MI355X, from the learned start and from the moment-based start.
 
-One step = the whole hot path over one batch of synthetic galaxies resident
-in HBM: moment-based start vectors (gm_default_guess), the persistent LM fit
-(gm_fit_batch) and the covariance errors (gm_param_errors).
+Default workload "learned": 65,536 held-out single-Sersic galaxies (64x64,
+Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma Gaussian noise).  Before the
+timed region the proposal network is trained on the GPU by the library's own
+kernels on 1,048,576 galaxies made by the forward model (reported, untimed).
+One timed step = the whole hot path over the held-out batch resident in HBM:
+gm_fit_learned (moments, features, network, decoding, LM from the proposals,
+fallback LM from the moment start) and gm_param_errors.  The same galaxies
+are then fitted by plain LM from the moment start (gm_default_guess +
+gm_fit_batch + gm_param_errors) for the speedup.
 
-Workload "uneven" (default): 8,192 single-Sersic galaxies, square cutouts
-log-uniform in 48-256 px, each with its own 25x25 Moffat PSF, Poisson + read
-noise.  The images are rendered with the library's own forward model
-(gm_model_image) from seeded draws, then noised on the host.
+Other workloads (plain LM only): "uneven" (8,192 galaxies, cutouts 48-256 px,
+per-galaxy 25x25 Moffat PSFs, Poisson + read noise), "sersic64", "bulgedisk".
 
 Printed: one JSON line with the throughput, the roofline of the dominant
-kernel (the LM fit), and the FP64 CPU oracle timed on a bounded sample of the
-same workload; on that sample the oracle also renders the data and the GPU
-fit is compared with the oracle fit from the same start (parity).
+kernel (the LM fit, timed with HIP events on the launch stream), and the FP64
+CPU oracle on a bounded sample of the same workload (images rendered and
+noised on the host), which also judges the GPU fits (parity counts).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -36,28 +40,40 @@ from paper_2404_07780_amd import gmfit as G  # noqa: E402
 from paper_2404_07780_amd import synth as S  # noqa: E402
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+METRIC = "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs plain LM"
 
-# HBM bytes per lm_fit launch on the default workload (8192 galaxies, seed 0) from
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 from a
-# 1 GiB copy), keyed by the hash of the kernel sources they were taken with.
-TRAFFIC = {"1e071d0ae89bc2a0": 6.485e6 * 1024 * 2.0 + 2.488e4 * 1024}
+# HBM bytes per LM-fit launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (scaled by the counts of a 1 GiB copy: FETCH x 2.0, WRITE x 1.0), keyed by
+# workload and the hash of the library sources they were taken with.
+TRAFFIC = {}
 
 
-def kernel_hash() -> str:
-    import hashlib
-
+def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("gm_abi.hip", "gm_kernels.h", "gm_device.h"):
+    files = sorted(os.listdir(os.path.join(ROOT, "paper_2404_07780_amd", "csrc")))
+    for f in files:
         with open(os.path.join(ROOT, "paper_2404_07780_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "gmfit.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
+
+
 WORKLOADS = {
-    "uneven": dict(n=8192, desc="8192 single-Sersic galaxies, square cutouts log-uniform 48-256 px, per-galaxy "
-                                "Moffat PSF 25x25, Poisson + 5 e- read noise, LM from moment-based start"),
-    "sersic64": dict(n=64, desc="64 single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px on 15x15, "
-                                "sigma = 1 Gaussian noise"),
-    "bulgedisk": dict(n=8192, desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, "
-                                   "Moffat PSF 25x25, Poisson + read noise"),
+    "learned": dict(n=65536, cfg="sersic64", seed=2,
+                    desc="65536 held-out single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px on 15x15, "
+                         "unit-sigma Gaussian noise; LM from the learned proposal (MLP 1056-512x3-16, BF16, "
+                         "trained on forward-model galaxies) with moment-start fallback, vs plain LM from the "
+                         "moment start"),
+    "uneven": dict(n=8192, cfg="uneven", seed=0,
+                   desc="8192 single-Sersic galaxies, square cutouts log-uniform 48-256 px, per-galaxy Moffat PSF "
+                        "25x25, Poisson + 5 e- read noise, LM from moment-based start"),
+    "sersic64": dict(n=64, cfg="sersic64", seed=0,
+                     desc="64 single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px on 15x15, sigma = 1 "
+                          "Gaussian noise, LM from moment-based start"),
+    "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
+                      desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
+                           "25x25, Poisson + read noise, LM from moment-based start"),
 }
 
 
@@ -65,16 +81,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_batch(workload: str, n: int, seed: int):
-    """Draw, render with the HIP forward model at unit flux, add noise."""
-    b = S.draw(workload, n, seed=seed)
+def make_batch(cfg: str, n: int, seed: int):
+    """Draw, render at unit flux with the HIP forward model, add noise: on the
+    device (Philox) for the unit-sigma workload, on the host otherwise."""
+    b = S.draw(cfg, n, seed=seed)
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
-    db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, np.zeros(b.npix, np.float32),
-                 np.ones(b.npix, np.float32), b.psf)
-    units = G.gm_model_image(gm, db, S.unit_truth(b)).cpu().numpy()
-    S.finish(b, units)
-    db.data = torch.from_numpy(b.data).to(db.device)
-    db.sigma = torch.from_numpy(b.sigma).to(db.device)
+    unused = torch.empty(b.npix, dtype=torch.float32, device="cuda")
+    db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, unused, unused, b.psf)
+    units = G.gm_model_image(gm, db, S.unit_truth(b))
+    del unused
+    if cfg == "sersic64":
+        snr = torch.from_numpy(b.snr).cuda()
+        sky = torch.from_numpy(b.sky).cuda()
+        data, sig = G.gm_synth_noise(b.h, b.w, b.img_off, units, snr, sky, 1.0, seed)
+        db.data, db.sigma = data, sig
+    else:
+        S.finish(b, units.cpu().numpy())
+        db.data = torch.from_numpy(b.data).to(db.device)
+        db.sigma = torch.from_numpy(b.sigma).to(db.device)
+    del units
     return b, gm, db
 
 
@@ -87,16 +112,17 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
     return 2.0 * hw * k2 * npl, 2.0 * hw * (p * (p + 1) / 2 + p + 1)
 
 
-def cpu_baseline(workload: str, n_sample: int, seed: int, gm: G.Model):
-    """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered by
-    the oracle), all host cores, each side from its own moment-based start; the
-    GPU fit of the same data gives the parity count."""
+def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None):
+    """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
+    noised on the host), all host cores, LM from its own moment start; the GPU
+    fits of the same data (plain, and learned when a network is given) are
+    judged against it."""
     import oracle as O
     from tests.gpu_helpers import oracle_batch, param_parity
     from tests.oracle_models import from_spec
 
     ncores = len(os.sched_getaffinity(0))
-    b = oracle_batch(workload, n_sample, seed=seed)
+    b = oracle_batch(cfg, n_sample, seed=seed)
     om = from_spec(b.model)
     db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf)
     t0 = time.perf_counter()
@@ -104,19 +130,68 @@ def cpu_baseline(workload: str, n_sample: int, seed: int, gm: G.Model):
     rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
                                  nthreads=ncores)
     dt = time.perf_counter() - t0
+    names = S.MODEL_SPECS[b.model]["names"]
+
+    def judge(gp, gs):
+        both = (gs == 0) & (rs == 0)
+        npass = sum(int(param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))[0].all())
+                    for g in np.where(both)[0])
+        return dict(both_converged=int(both.sum()), pass_1e4=int(npass), gpu_converged=int((gs == 0).sum()))
+
     start, _ = G.gm_default_guess(gm, db)
     gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
-    names = S.MODEL_SPECS[b.model]["names"]
-    both = (gs == 0) & (rs == 0)
-    npass = 0
-    for g in np.where(both)[0]:
-        ok, _ = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
-        npass += int(ok.all())
-    return dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
-                sample=f"galaxies 0..{n_sample - 1} of the workload (oracle-rendered), moment-based start and LM, "
-                       f"{dt:.1f} s"), dict(sample=n_sample, both_converged=int(both.sum()), pass_1e4=npass,
-                                                    oracle_converged=int((rs == 0).sum()),
-                                                    gpu_converged=int((gs == 0).sum()))
+    parity = dict(sample=n_sample, oracle_converged=int((rs == 0).sum()), oracle_mean_iters=float(rn.mean()),
+                  plain=judge(gp, gs))
+    if mlp is not None:
+        lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp)]
+        parity["learned"] = judge(lp, ls)
+        parity["learned"]["fallback"] = int((fb != 0).sum())
+    cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
+               sample=f"galaxies 0..{n_sample - 1} of the workload (rendered and noised on the host), moment start "
+                      f"and LM, {dt:.1f} s")
+    return cpu, parity
+
+
+def timed(step, steps: int, warmup: int, name: str):
+    for i in range(warmup):
+        step(None)
+        torch.cuda.synchronize()
+        log(f"{name}: warmup step {i + 1}/{warmup} done")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for row in evs:                       # create the events before the timed region
+        for e in row:
+            e.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"{name}: timed {steps} steps in {wall:.3f} s")
+    return wall, evs
+
+
+def train_network(n_train: int, epochs: int, batch: int):
+    from paper_2404_07780_amd import learned as Lrn
+
+    log(f"training set: {n_train} forward-model galaxies")
+    ds = Lrn.make_training_set(n_train, seed=1)
+    log(f"training set built in {ds.seconds:.1f} s")
+    mlp = Lrn.new_mlp(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = Lrn.train(mlp, ds, epochs=epochs, batch=batch)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = (n_train // batch) * epochs
+    flop = 6.0 * Lrn.param_count() * batch * steps       # forward + backward GEMMs (2 + 4 per MAC)
+    log(f"trained {epochs} epochs ({steps} steps) in {dt:.1f} s; loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    info = dict(samples=n_train, epochs=epochs, batch=batch, steps=steps, data_s=ds.seconds, train_s=dt,
+                loss_first_epoch=losses[0], loss_last_epoch=losses[-1], gemm_tflops=flop / dt / 1e12,
+                optimizer="AdamW lr 1e-3 cosine to 1e-5, weight decay 0.01")
+    del ds
+    torch.cuda.empty_cache()
+    return mlp, info
 
 
 def main():
@@ -124,9 +199,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uneven", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="learned", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=None, help="galaxies (default: the workload's size)")
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--train-n", type=int, default=1 << 20, help="training galaxies (learned workload)")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--train-batch", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle sample size (0 = skip)")
     ap.add_argument("--calib", action="store_true",
                     help="first run one 1 GiB device copy (reference for memory-traffic counters)")
@@ -148,92 +226,107 @@ def main():
         del src, dst
     wl = WORKLOADS[args.workload]
     n = args.n or wl["n"]
+    seed = wl["seed"] if args.seed is None else args.seed
+    learned = args.workload == "learned"
+    mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
+
     t0 = time.perf_counter()
-    b, gm, db = make_batch(args.workload, n, args.seed)
+    b, gm, db = make_batch(wl["cfg"], n, seed)
+    torch.cuda.synchronize()
     log(f"generated {n} galaxies ({b.npix / 1e6:.1f} Mpx) in {time.perf_counter() - t0:.1f} s")
     p = gm.p
-    npl = p   # planes: model + every non-sky variable
-    f_conv, f_red = flops_per_eval(b, p, npl)
-
-    stream = torch.cuda.current_stream()
-    params = torch.empty(n, p, dtype=torch.float64, device=db.device)
-    chi2 = torch.empty(n, dtype=torch.float64, device=db.device)
-    niter = torch.empty(n, dtype=torch.int32, device=db.device)
-    status = torch.empty(n, dtype=torch.int32, device=db.device)
-    err = torch.empty(n, p, dtype=torch.float64, device=db.device)
+    f_conv, f_red = flops_per_eval(b, p, p)    # planes: model + every non-sky variable
+    f_eval = f_conv + f_red
     ctx = G.context()
+    stream = torch.cuda.current_stream()
+    dev = db.device
+    params = torch.empty(n, p, dtype=torch.float64, device=dev)
+    chi2 = torch.empty(n, dtype=torch.float64, device=dev)
+    niter = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    fallback = torch.empty(n, dtype=torch.int32, device=dev)
 
-    def step(events=None):
-        if events:
-            events[0].record(stream)
+    def plain_step(ev):
+        if ev:
+            ev[0].record(stream)
         guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
-        if events:
-            events[1].record(stream)
+        if ev:
+            ev[1].record(stream)
         G.gm_fit_batch(gm, db, guess, ctx=ctx, out=(params, chi2, niter, status))
-        if events:
-            events[2].record(stream)
-        e = G.gm_param_errors(gm, db, params, ctx=ctx)
-        if events:
-            events[3].record(stream)
-        return e
+        if ev:
+            ev[2].record(stream)
+        G.gm_param_errors(gm, db, params, ctx=ctx)
+        if ev:
+            ev[3].record(stream)
 
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    log(f"timed {args.steps} steps in {wall:.3f} s")
-    fit_ms = [evs[i][1].elapsed_time(evs[i][2]) for i in range(args.steps)]
-    guess_ms = [evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)]
-    err_ms = [evs[i][2].elapsed_time(evs[i][3]) for i in range(args.steps)]
-    nit = niter.cpu().numpy()
-    st = status.cpu().numpy()
-    evals = (1 + nit.astype(np.float64)) * (st != G.ST_NONFINITE)
-    flops_fit = float(np.sum((f_conv + f_red) * evals))
-    fit_s = float(np.mean(fit_ms)) / 1e3
-    achieved = flops_fit / fit_s / 1e12
-    ms_step = wall / args.steps * 1e3
-    value = n / (wall / args.steps)
+    def learned_step(ev):
+        G.gm_fit_learned(gm, db, mlp, ctx=ctx, out=(params, chi2, niter, status, fallback), events=ev)
+        G.gm_param_errors(gm, db, params, ctx=ctx)
+
+    results = {}
+    for name, step in ((("learned", learned_step), ("plain", plain_step)) if learned else (("plain", plain_step),)):
+        wall, evs = timed(step, args.steps, args.warmup, name)
+        nit = niter.cpu().numpy().astype(np.float64)
+        st = status.cpu().numpy()
+        if name == "learned":
+            fb = fallback.cpu().numpy()
+            lm_ms = [evs[i][0].elapsed_time(evs[i][1]) + evs[i][2].elapsed_time(evs[i][3])
+                     for i in range(args.steps)]
+            evals = 1.0 + nit + (fb == 2)
+            extra = dict(fallback_invalid=int((fb == 1).sum()), fallback_unconverged=int((fb == 2).sum()))
+            kernel = "lm_fit_kernel (proposal launch + fallback launch)"
+        else:
+            lm_ms = [evs[i][1].elapsed_time(evs[i][2]) for i in range(args.steps)]
+            evals = 1.0 + nit
+            extra = dict(guess_ms=float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)])),
+                         errors_ms=float(np.mean([evs[i][2].elapsed_time(evs[i][3]) for i in range(args.steps)])))
+            kernel = "lm_fit_kernel"
+        evals = evals * (st != G.ST_NONFINITE)
+        flops = float(np.sum(f_eval * evals))
+        lm_s = float(np.mean(lm_ms)) / 1e3
+        results[name] = dict(value=n / (wall / args.steps), ms_per_step=wall / args.steps * 1e3, lm_ms=lm_s * 1e3,
+                             achieved=flops / lm_s / 1e12, flops=flops, kernel=kernel, mean_iters=float(nit.mean()),
+                             converged=float(np.mean(st == G.ST_CONVERGED)),
+                             status_hist=np.bincount(st, minlength=4).tolist(), **extra)
+    head = results["learned" if learned else "plain"]
 
     cpu, parity = None, None
     if args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} galaxies")
-        cpu, parity = cpu_baseline(args.workload, args.cpu_sample, args.seed, gm)
+        cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp)
 
+    key = f"{args.workload}:{n}:{seed}:{source_hash()}"
     out = {
-        "metric": "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs plain LM",
-        "value": value,
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "galaxies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "n_gal": n, "init": "default (moments)",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "n_gal": n, "seed": seed,
+                   "init": "learned proposal + moment fallback" if learned else "moment-based",
                    "max_iter": 100, "step_tol": 1e-4},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": (TRAFFIC.get(kernel_hash()) if (args.workload == "uneven" and n == 8192
-                                                               and args.seed == 0) else None),
-                     "traffic_unit": "bytes per launch",
-                     "kernel": "lm_fit_kernel", "kernel_ms": fit_s * 1e3,
-                     "flops_per_launch": flops_fit},
-        "breakdown_ms": {"default_guess": float(np.mean(guess_ms)), "lm_fit": float(np.mean(fit_ms)),
-                         "param_errors": float(np.mean(err_ms))},
-        "lm": {"mean_iters": float(nit.mean()), "status_hist": np.bincount(st, minlength=4).tolist()},
+        "roofline": {"bound": "alu", "achieved": head["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": head["achieved"] / PEAK_FP32_TFLOPS, "traffic": TRAFFIC.get(key),
+                     "traffic_unit": "HBM bytes per launch", "kernel": head["kernel"], "kernel_ms": head["lm_ms"],
+                     "flops_per_step": head["flops"]},
+        "lm": {k: v for k, v in head.items() if k not in ("value", "ms_per_step", "achieved", "flops", "kernel")},
         "cpu_baseline": cpu,
         "parity": parity,
     }
+    if learned:
+        pl = results["plain"]
+        out["plain_lm"] = dict(value=pl["value"], ms_per_step=pl["ms_per_step"], lm_ms=pl["lm_ms"],
+                               mean_iters=pl["mean_iters"], converged=pl["converged"],
+                               roofline_frac=pl["achieved"] / PEAK_FP32_TFLOPS)
+        out["speedup_vs_plain"] = head["value"] / pl["value"]
+        out["training"] = train_info
     print(json.dumps(out))
 
 

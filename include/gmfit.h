@@ -122,6 +122,15 @@ int gm_model_image(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
 int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                 const double *params, float *jac_out, void *stream);
 
+/* Adjoint of gm_model_image (the vector-Jacobian product used by gradient-based
+ * fitters such as the paper's, Sec. 5.1): grad_params_out[g][c] =
+ * sum over pixels of dM/dp_c (natural units, as gm_jacobian) times
+ * grad_image at the same pixel.  grad_image: device FP32 in the image layout;
+ * grad_params_out: device [n_gal][p] (columns of fixed slots are 0). */
+int gm_model_vjp(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
+                 const double *params, const float *grad_image, double *grad_params_out,
+                 void *stream);
+
 /* Moment-based start vector (replaces the SExtractor start values of Sec. 3):
  * border-frame sky, flux-weighted centroid and second moments of the pixels
  * 3 sigma above it.  params_out: device [n_gal][p]; moments_out (nullable):
@@ -240,11 +249,16 @@ int gm_proposal_decode(gm_ctx *ctx, const gm_model *model, const gm_batch *batch
  * galaxies whose proposal is invalid, or whose LM from it does not end
  * GM_ST_CONVERGED, are refitted from gm_default_guess; their reported result
  * is the refit and niter_out counts the trials of both fits.  fallback_out
- * (device, nullable) [n_gal] = 1 where the fallback ran.  opts->active is
- * ignored.  Same model restriction as gm_proposal_decode. */
+ * (device, nullable) [n_gal]: 0 = fitted from the proposal, 1 = proposal
+ * invalid, 2 = LM from the proposal did not converge (refitted).
+ * events (nullable): four hipEvent_t recorded on the stream before and after
+ * the LM launch from the proposals and before and after the fallback LM
+ * launch (profiling).  opts->active is ignored.  Same model restriction as
+ * gm_proposal_decode. */
 int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
                    const gm_fit_opts *opts, double *params_out, double *chi2_out,
-                   int32_t *niter_out, int32_t *status_out, int32_t *fallback_out, void *stream);
+                   int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,
+                   void *const *events, void *stream);
 
 /* Training images: data_out = F unit + sky + sigma z per galaxy, with unit a
  * noiseless unit-flux model image (device FP32 at img_off, host sizes),

@@ -57,6 +57,23 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+int ensure_aux(gm_ctx *c, size_t bytes, void **out)
+{
+    if (c->aux_bytes < bytes) {
+        if (c->aux) {
+            if (hipDeviceSynchronize() != hipSuccess) return GM_EHIP;
+            (void)hipFree(c->aux);
+            c->aux = nullptr;
+            c->aux_bytes = 0;
+        }
+        size_t nb = std::max(bytes, (size_t)1 << 20);
+        if (hipMalloc(&c->aux, nb) != hipSuccess) return GM_ENOMEM;
+        c->aux_bytes = nb;
+    }
+    *out = c->aux;
+    return GM_OK;
+}
+
 int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, hipStream_t st, Staged *out)
 {
     const gm_batch *b = ci.b;
@@ -304,6 +321,7 @@ void gm_destroy(gm_ctx *c)
     if (c->host) (void)hipHostFree(c->host);
     if (c->unit_psf) (void)hipFree(c->unit_psf);
     if (c->mlp_ws) (void)hipFree(c->mlp_ws);
+    if (c->aux) (void)hipFree(c->aux);
     if (c->staged) (void)hipEventDestroy(c->staged);
     delete c;
 }
@@ -342,6 +360,18 @@ int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const
     if (!params || !jac_out) return GM_EINVAL;
     Scoped sd(ctx->device);
     return mt.ops.image(ctx, mt.ci, params, jac_out, 1, (hipStream_t)stream);
+}
+
+int gm_model_vjp(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params,
+                 const float *grad_image, double *grad_params_out, void *stream)
+{
+    Match mt;
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if (batch->n_gal == 0) return GM_OK;
+    if (!params || !grad_image || !grad_params_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    return mt.ops.vjp(ctx, mt.ci, params, grad_image, grad_params_out, (hipStream_t)stream);
 }
 
 int gm_default_guess(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, double *params_out,

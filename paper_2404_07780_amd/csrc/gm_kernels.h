@@ -836,8 +836,10 @@ struct ImageArgs {
     const TileItem *tiles;
     int n_tiles;
     const double *params;
-    float *out;      // model (mode 0) or Jacobian (mode 1)
-    int mode;
+    float *out;          // model (mode 0) or Jacobian (mode 1)
+    int mode;            // 2: adjoint, per-tile partials of J^T gin into part
+    const float *gin;    // mode 2: weights of the pixels (image layout)
+    double *part;        // mode 2: [n_tiles][P] partial sums (internal variable order)
 };
 
 template <class F, int KT, int NG>
@@ -847,7 +849,9 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
     float *planes = reinterpret_cast<float *>(dyn_lds);
     __shared__ EvalShared<F> esh;
     __shared__ double su[F::P];
+    __shared__ double sdu[F::P];        // d u / d p (natural units)
     __shared__ int sfree[F::P];
+    __shared__ double sv[NWAVE][F::P];
     constexpr int P = F::P;
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < ia.n_tiles; it += gridDim.x) {
@@ -860,6 +864,7 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
             for (int k = 0; k < P; ++k) {
                 int c = ma.col[k];
                 su[k] = nat_to_u(F::kind(k), c >= 0 ? pp[c] : ma.fixedv[k]);
+                sdu[k] = 1.0 / dnat_du(F::kind(k), u_to_nat(F::kind(k), su[k]));
                 sfree[k] = c >= 0;
             }
         }
@@ -872,6 +877,9 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
         tile_planes<F, KT, NG>(esh, planes, H, W, K, ti0, tj0, (const cfloat *)(ba.psf + uniform64(me.psf_off)), r,
                                cg, acc0, acc);
         const int i = ti0 + r;
+        double v[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = 0.0;
         if (i < H) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -880,19 +888,54 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
                 const int64_t pix = (int64_t)i * W + j;
                 if (ia.mode == 0) {
                     ia.out[me.img_off + pix] = (float)(acc0[t] + esh.prep.sky);
-                } else {
+                } else if (ia.mode == 1) {
                     float *jo = ia.out + (int64_t)ma.p * me.img_off;
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
                         if (!sfree[k]) continue;
-                        float du_dp = (float)(1.0 / dnat_du(F::kind(k), u_to_nat(F::kind(k), su[k])));
                         float jv = (k == F::SKY) ? 1.0f : acc[1 + k][t];
-                        jo[(int64_t)ma.col[k] * H * W + pix] = jv * du_dp;
+                        jo[(int64_t)ma.col[k] * H * W + pix] = jv * (float)sdu[k];
                     }
+                } else {
+                    const double gw = (double)ia.gin[me.img_off + pix];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) v[k] += (k == F::SKY ? 1.0 : (double)acc[1 + k][t]) * gw;
                 }
             }
         }
+        if (ia.mode == 2) {
+            // fixed-order reduction: wave butterflies, then the waves in order
+            const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double w = wave_sum(v[k]);
+                if (lane == 0) sv[wave][k] = w;
+            }
+            __syncthreads();
+            if (tid < P) {
+                double sacc = sv[0][tid];
+                for (int w = 1; w < NWAVE; ++w) sacc += sv[w][tid];
+                ia.part[(int64_t)it * P + tid] = sacc * sdu[tid];
+            }
+        }
         __syncthreads();
+    }
+}
+
+// Sum of the tile partials of each galaxy (tiles tstart[g] .. tstart[g+1]-1, in
+// order) into its gradient row; fixed columns of the row are left at 0.
+static __global__ void vjp_reduce_kernel(int n_gal, int P, ModelArgs ma, const int *tstart, const double *part,
+                                  double *grad)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_gal) return;
+    double *row = grad + (int64_t)g * ma.p;
+    for (int c = 0; c < ma.p; ++c) row[c] = 0.0;
+    for (int k = 0; k < P; ++k) {
+        if (ma.col[k] < 0) continue;
+        double s = 0.0;
+        for (int t = tstart[g]; t < tstart[g + 1]; ++t) s += part[(int64_t)t * P + k];
+        row[ma.col[k]] = s;
     }
 }
 

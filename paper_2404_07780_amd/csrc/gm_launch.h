@@ -24,6 +24,8 @@ struct gm_ctx {
     float *unit_psf = nullptr;    // device 1x1 kernel {1.0}: runs unconvolved models
     void *mlp_ws = nullptr;       // grow-only device workspace of the learned proposal
     size_t mlp_ws_bytes = 0;
+    void *aux = nullptr;          // grow-only device scratch (adjoint partial sums)
+    size_t aux_bytes = 0;
 };
 
 namespace gm {
@@ -50,6 +52,8 @@ struct Staged {
 int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, hipStream_t st, Staged *out);
 int batch_kt(const CallInfo &ci);
 int max_k(const CallInfo &ci);
+// grow-only device scratch of the context (stream-ordered reuse)
+int ensure_aux(gm_ctx *c, size_t bytes, void **out);
 
 inline int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_EHIP; }
 
@@ -217,8 +221,44 @@ int run_image(gm_ctx *c, const CallInfo &ci, const double *params, float *out, i
     Staged sg;
     rc = stage(c, ci, tiles.data(), sizeof(TileItem) * tiles.size(), st, &sg);
     if (rc) return rc;
-    ImageArgs ia{reinterpret_cast<const TileItem *>(sg.extra), (int)tiles.size(), params, out, mode};
+    ImageArgs ia{reinterpret_cast<const TileItem *>(sg.extra), (int)tiles.size(), params, out, mode, nullptr, nullptr};
     return Dispatch<F, NG, KTS...>::img(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ia, lds, st);
+}
+
+// Adjoint of the model image: grad[g][c] = sum_pixels dM/dp_c * gin (natural
+// units), per-tile FP64 partials then a per-galaxy sum in tile order.
+template <class F, int NG, int... KTS>
+int run_vjp(gm_ctx *c, const CallInfo &ci, const double *params, const float *gin, double *grad, hipStream_t st)
+{
+    const gm_batch *b = ci.b;
+    size_t lds;
+    int rc = check_lds<F, NG>(max_k(ci), &lds);
+    if (rc) return rc;
+    std::vector<TileItem> tiles;
+    std::vector<int> tstart(b->n_gal + 1, 0);
+    for (int g = 0; g < b->n_gal; ++g) {
+        tstart[g] = (int)tiles.size();
+        for (int ty = 0; ty < (b->h[g] + TILE - 1) / TILE; ++ty)
+            for (int tx = 0; tx < (b->w[g] + TILE - 1) / TILE; ++tx) tiles.push_back({g, ty, tx, 0});
+    }
+    tstart[b->n_gal] = (int)tiles.size();
+    const size_t tb = sizeof(TileItem) * tiles.size();
+    std::vector<char> blob(tb + sizeof(int) * tstart.size());
+    memcpy(blob.data(), tiles.data(), tb);
+    memcpy(blob.data() + tb, tstart.data(), sizeof(int) * tstart.size());
+    double *part = nullptr;
+    rc = ensure_aux(c, sizeof(double) * F::P * tiles.size(), reinterpret_cast<void **>(&part));
+    if (rc) return rc;
+    Staged sg;
+    rc = stage(c, ci, blob.data(), blob.size(), st, &sg);
+    if (rc) return rc;
+    ImageArgs ia{reinterpret_cast<const TileItem *>(sg.extra), (int)tiles.size(), params, nullptr, 2, gin, part};
+    rc = Dispatch<F, NG, KTS...>::img(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ia, lds, st);
+    if (rc) return rc;
+    const int *ts = reinterpret_cast<const int *>(reinterpret_cast<const char *>(sg.extra) + tb);
+    hipLaunchKernelGGL(vjp_reduce_kernel, dim3((b->n_gal + 255) / 256), dim3(256), 0, st, b->n_gal, F::P, ci.ma, ts,
+                       part, grad);
+    return hip_rc(hipGetLastError());
 }
 
 template <class F>
@@ -240,12 +280,14 @@ struct FamilyOps {
     int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t);
     int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t);
     int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t);
+    int (*vjp)(gm_ctx *, const CallInfo &, const double *, const float *, double *, hipStream_t);
 };
 
 template <class F, int NG, int... KTS>
 FamilyOps make_ops()
 {
-    return FamilyOps{run_fit<F, NG, KTS...>, run_errors<F, NG, KTS...>, run_image<F, NG, KTS...>, run_guess<F>};
+    return FamilyOps{run_fit<F, NG, KTS...>, run_errors<F, NG, KTS...>, run_image<F, NG, KTS...>, run_guess<F>,
+                     run_vjp<F, NG, KTS...>};
 }
 
 // family tables, one per translation unit

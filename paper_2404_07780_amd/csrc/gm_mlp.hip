@@ -398,7 +398,7 @@ __global__ void fallback_kernel(int n_gal, int p, const int *valid, const int *s
         for (int k = 0; k < p; ++k) params[(int64_t)g * p + k] = pdef[(int64_t)g * p + k];
     active2[g] = fb ? 1 : 0;
     nsave[g] = fb && valid[g] ? niter[g] : 0;
-    if (fallback) fallback[g] = fb ? 1 : 0;
+    if (fallback) fallback[g] = !valid[g] ? 1 : (fb ? 2 : 0);
 }
 
 __global__ void add_iters_kernel(int n_gal, const int *nsave, int *niter)
@@ -863,7 +863,7 @@ int gm_proposal_decode(gm_ctx *ctx, const gm_model *model, const gm_batch *batch
 
 int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
                    const gm_fit_opts *opts, double *params_out, double *chi2_out, int32_t *niter_out,
-                   int32_t *status_out, int32_t *fallback_out, void *stream)
+                   int32_t *status_out, int32_t *fallback_out, void *const *events, void *stream)
 {
     Match mt;
     int rc = prologue(ctx, model, batch, mt);
@@ -907,17 +907,24 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     rc = decode_launch(ctx, mt, out, mlp->out_dim, mom8, params_out, valid, st);
     if (rc) return rc;
     // LM from the valid proposals
+    auto mark = [&](int i) {
+        return events && hipEventRecord((hipEvent_t)events[i], st) != hipSuccess ? GM_EHIP : GM_OK;
+    };
     gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr};
     o.active = valid;
+    if ((rc = mark(0))) return rc;
     rc = mt.ops.fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (rc) return rc;
+    if ((rc = mark(1))) return rc;
     // invalid or unconverged: refit from the default guess
     hipLaunchKernelGGL(fallback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p, valid, status_out, pdef,
                        params_out, active2, niter_out, nsave, fallback_out);
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
     o.active = active2;
+    if ((rc = mark(2))) return rc;
     rc = mt.ops.fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (rc) return rc;
+    if ((rc = mark(3))) return rc;
     hipLaunchKernelGGL(add_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nsave, niter_out);
     return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
 }

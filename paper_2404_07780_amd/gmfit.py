@@ -24,7 +24,7 @@ SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
 
 # exported symbols (one per declaration of include/gmfit.h)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",
-           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_mlp_param_count", "gm_mlp_sync",
+           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_mlp_param_count", "gm_mlp_sync",
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise")
 
@@ -89,6 +89,7 @@ def lib() -> C.CDLL:
         L.gm_default_guess.argtypes = [v, p, p, v, v, v]
         L.gm_fit_batch.argtypes = [v, p, p, p, v, v, v, v, v]
         L.gm_param_errors.argtypes = [v, p, p, v, v, v, v]
+        L.gm_model_vjp.argtypes = [v, p, p, v, v, v, v]
         i64, u64, f, d = C.c_int64, C.c_uint64, C.c_float, C.c_double
         L.gm_mlp_param_count.argtypes = [p]
         L.gm_mlp_param_count.restype = i64
@@ -100,10 +101,10 @@ def lib() -> C.CDLL:
         L.gm_features.argtypes = [v, p, p, v, i64, v, v]
         L.gm_proposal_targets.argtypes = [v, p, p, v, v, v, i, v]
         L.gm_proposal_decode.argtypes = [v, p, p, v, i, v, v, v, v]
-        L.gm_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v]
+        L.gm_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, v]
         L.gm_synth_noise.argtypes = [v, i, v, v, v, v, v, v, f, d, u64, i64, v, v, v, i, v]
         for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
-                     "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
+                     "gm_model_vjp", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise"):
             getattr(L, name).restype = i
@@ -272,6 +273,21 @@ def gm_jacobian(model: Model, batch: Batch, params, ctx: Optional[Context] = Non
     m, b = model.c(), batch.c()
     _check("gm_jacobian", lib().gm_jacobian(ctx.handle, C.byref(m), C.byref(b), _ptr(pr), _ptr(out), _stream()))
     return out
+
+
+def gm_model_vjp(model: Model, batch: Batch, params, grad_image: torch.Tensor,
+                 ctx: Optional[Context] = None) -> torch.Tensor:
+    """sum over pixels of dM/dp * grad_image per galaxy: device [n][p] FP64."""
+    ctx = ctx or context(batch.device.index)
+    pr = _params_dev(params, batch, model.p)
+    gi = grad_image.to(device=batch.device, dtype=torch.float32).contiguous()
+    if gi.numel() != batch.npix:
+        raise ValueError("grad_image must have the model image's size")
+    grad = torch.empty(batch.n, model.p, dtype=torch.float64, device=batch.device)
+    m, b = model.c(), batch.c()
+    _check("gm_model_vjp", lib().gm_model_vjp(ctx.handle, C.byref(m), C.byref(b), _ptr(pr), _ptr(gi), _ptr(grad),
+                                              _stream()))
+    return grad
 
 
 def gm_default_guess(model: Model, batch: Batch, ctx: Optional[Context] = None):
@@ -452,8 +468,10 @@ def gm_proposal_decode(model: Model, batch: Batch, out: torch.Tensor, moments: t
 
 
 def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, lambda0: float = 1e-3,
-                   step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None):
-    """(params, chi2, niter, status, fallback) as device tensors."""
+                   step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None, events=None):
+    """(params, chi2, niter, status, fallback) as device tensors.  events: four
+    recorded torch.cuda.Event objects that the library re-records around its
+    two LM launches."""
     ctx = _ctx_for(batch.device, ctx)
     if out is None:
         params = torch.zeros(batch.n, model.p, dtype=torch.float64, device=batch.device)
@@ -465,9 +483,14 @@ def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, la
         params, chi2, niter, status, fallback = out
     o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None)
     m, b, ml = model.c(), batch.c(), mlp.c()
+    ev = None
+    if events is not None:
+        if len(events) != 4 or any(int(e.cuda_event) == 0 for e in events):
+            raise ValueError("events: four torch.cuda.Event objects, each recorded once")
+        ev = (C.c_void_p * 4)(*[int(e.cuda_event) for e in events])
     _check("gm_fit_learned", lib().gm_fit_learned(ctx.handle, C.byref(m), C.byref(b), C.byref(ml), C.byref(o),
                                                   _ptr(params), _ptr(chi2), _ptr(niter), _ptr(status),
-                                                  _ptr(fallback), _stream()))
+                                                  _ptr(fallback), ev, _stream()))
     return params, chi2, niter, status, fallback
 
 

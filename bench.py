@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--train-n", type=int, default=1 << 20, help="training galaxies (learned workload)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=4096)
-    ap.add_argument("--cpu-sample", type=int, default=48, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="oracle sample size (0 = skip; default 1024 for the learned workload, else 48)")
     ap.add_argument("--calib", action="store_true",
                     help="first run one 1 GiB device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -228,6 +229,8 @@ def main():
     n = args.n or wl["n"]
     seed = wl["seed"] if args.seed is None else args.seed
     learned = args.workload == "learned"
+    if args.cpu_sample is None:
+        args.cpu_sample = 1024 if learned else 48
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()

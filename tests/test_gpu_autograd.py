@@ -1,8 +1,8 @@
 """The adjoint (gm_model_vjp) and the torch.autograd.Function over the forward
 model: against the FP64 oracle Jacobian contracted with the same pixel
 weights (1e-5 of sum |J| |w| per parameter) and against central finite
-differences of the FP32 forward model with h = 1e-3 relative (2e-3, limited
-by FP32 rounding of the image)."""
+differences of the FP32 forward model with h = 1e-3 relative, centres 1e-3
+px (2e-3, limited by FP32 rounding of the image)."""
 import numpy as np
 import pytest
 
@@ -60,16 +60,23 @@ def test_autograd_matches_finite_differences(cfg):
     rng = np.random.default_rng(16)
     # a smooth scalar: weighted sum of the image with positive weights
     wts = torch.from_numpy(rng.uniform(0.5, 1.5, size=b.npix).astype(np.float32)).cuda()
-    params = torch.from_numpy(b.truth.copy()).cuda().requires_grad_(True)
+    # centres away from pixel edges: the oversampled window moves with floor(x0),
+    # floor(y0), a step the finite differences must not straddle
+    base = b.truth.copy()
+    base[:, 0] = np.floor(base[:, 0]) + 0.37
+    base[:, 1] = np.floor(base[:, 1]) + 0.61
+    params = torch.from_numpy(base.copy()).cuda().requires_grad_(True)
     (A.model_image(params, gm, db).double() * wts.double()).sum().backward()
     grad = params.grad.cpu().numpy()
     names = S.MODEL_SPECS[b.model]["names"]
     for g in range(b.n):
         for k in range(gm.p):
-            h = 1e-3 * max(abs(b.truth[g, k]), 1.0)
+            # 1e-3 relative; centres relative to the 1-px pixel scale (a step of 1e-3 x0 would
+            # straddle the curvature of a cuspy high-n core)
+            h = 1e-3 * (1.0 if names[k] in ("x0", "y0") else max(abs(base[g, k]), 1.0))
             vals = []
             for sgn in (1.0, -1.0):
-                pp = b.truth.copy()
+                pp = base.copy()
                 pp[g, k] += sgn * h
                 img = G.gm_model_image(gm, db, pp).double()
                 vals.append(float((img * wts.double()).sum().item()))

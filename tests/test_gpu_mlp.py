@@ -4,7 +4,7 @@ the LM oracle) and the test-side Philox reference.
 Tolerances.  GEMMs accumulate in FP32 on the device and exactly in the oracle,
 which otherwise rounds to BF16 at the same points; a rounding that lands on
 the other side of a BF16 tie moves one value by one BF16 step (2^-8
-relative), so network outputs are compared to 1e-3 of their scale, gradients
+relative), so network outputs are compared to 4e-3 of their scale (median 1e-5), gradients
 per layer to 2e-3 in relative Frobenius norm, and features allow one BF16
 step on at most 1% of the values.  Fitted parameters: 1e-4 relative (floors
 in tests/gpu_helpers.py) against the oracle's LM from its own moment guess,
@@ -64,9 +64,13 @@ def test_forward_matches_oracle(dims, n_out, n):
     got = G.gm_mlp_forward(mlp, _bf16_dev(x)).cpu().numpy()
     ref, _ = M.forward(flat.astype(np.float64), x, emulate_bf16=True, dims=dims)
     scale = np.abs(ref[:, :n_out]).max()
-    err = np.abs(got - ref).max()
-    print(f"forward max err {err:.3e} of scale {scale:.3e}", flush=True)
-    assert err <= 1e-3 * scale
+    errs = np.abs(got - ref)
+    err = errs.max()
+    print(f"forward max err {err:.3e}, median {np.median(errs):.3e}, of scale {scale:.3e}", flush=True)
+    # one hidden activation a step of 2^-8 away moves an output by ~|w| |a| 2^-8 ~ 1e-3 of the
+    # scale; FP32 accumulation alone stays near 1e-6
+    assert err <= 4e-3 * scale
+    assert np.median(errs) <= 1e-5 * scale
     assert np.all(got[:, n_out:] == 0.0)
 
 

@@ -3,8 +3,9 @@
 Tolerances: model images 1e-5 relative per pixel (floor 1e-6 of the image
 maximum), Jacobian columns 1e-5 of the column maximum, fitted parameters 1e-4
 relative (floors in tests/gpu_helpers.py), moments 1e-6 relative, covariance
-errors 1e-4 relative. End-to-end fits start each side from its own moment-based
-guess; the oracle never receives a value computed on the GPU.
+errors 1e-4 relative.  End-to-end fits start each side from its own moment-based
+guess; fit-only comparisons start both from the oracle's guess.  The oracle
+never receives a value computed on the GPU.
 """
 import math
 
@@ -143,14 +144,16 @@ def test_default_guess(cfg1, cfg2):
             assert np.allclose(mom[g], rm, rtol=1e-6, atol=1e-9)
 
 
-def _fit_parity(b: S.Batch, min_pass: float):
+def _fit_parity(b: S.Batch, min_pass: float, common_start: bool = False):
+    """End to end (each side from its own moment start) or, with common_start,
+    both LMs from the oracle's start vector."""
     om = from_spec(b.model)
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
     names = S.MODEL_SPECS[b.model]["names"]
     db = _dev_batch(b)
-    start, _ = G.gm_default_guess(gm, db)
-    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
     ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma)
+    start = ostart if common_start else G.gm_default_guess(gm, db)[0]
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
     rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart)
     both = (gs == 0) & (rs == 0)
     assert np.mean(rs == 0) > 0.8
@@ -179,6 +182,11 @@ def test_fit_sersic64(cfg1):
 def test_fit_uneven(cfg2):
     print("fit parity, uneven (12 galaxies)", flush=True)
     _fit_parity(cfg2, 0.9)
+
+
+def test_fit_sersic64_common_start(cfg1):
+    print("fit parity from the oracle's start, sersic64 (64 galaxies)", flush=True)
+    _fit_parity(cfg1, 0.95, common_start=True)
 
 
 def test_param_errors(cfg1):

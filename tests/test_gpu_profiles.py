@@ -117,9 +117,10 @@ def test_mixed_fit(mixed, kind):
     om = from_spec(b.model)
     gmod = to_gm(om)
     db = _dev(b)
-    start, _ = G.gm_default_guess(gmod, db)
-    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gmod, db, start)]
+    # both LMs from the oracle's moment start (the guess kernel is checked on its own above):
+    # two-component fits are too degenerate for starts 1e-9 apart to end in one minimum
     ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, omega=b.omega)
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gmod, db, ostart)]
     rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
                                  omega=b.omega)
     names = S.MODEL_SPECS[b.model]["names"]
@@ -127,6 +128,13 @@ def test_mixed_fit(mixed, kind):
     npass, fails = 0, []
     for g in np.where(both)[0]:
         ok, worst = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
+        if kind == "sersicbar" and rp[g, names.index("rout")] <= 0.1 + 1e-9:
+            # the bar collapsed onto the r_out bound: it covers no sample point, adds nothing to
+            # the model, and its flux and shape are not identifiable.  Compare the unique part
+            # (Sersic + sky) and require the GPU's bar to have collapsed as well.
+            unique = [k for k, nm in enumerate(names) if nm not in ("mag_bar", "rout", "q_bar", "pa_bar")]
+            ok, worst = ok[unique], worst[unique]
+            ok = np.append(ok, gp[g, names.index("rout")] <= 0.1 + 1e-9)
         if ok.all():
             npass += 1
         else:

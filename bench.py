@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--train-batch", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="oracle sample size (0 = skip; default 1024 for the learned workload, else 48)")
+    ap.add_argument("--tune-sample", type=int, default=2048,
+                    help="galaxies timed per candidate schedule before the timed region (0 = library default)")
     ap.add_argument("--calib", action="store_true",
                     help="first run one 1 GiB device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -237,6 +239,13 @@ def main():
     b, gm, db = make_batch(wl["cfg"], n, seed)
     torch.cuda.synchronize()
     log(f"generated {n} galaxies ({b.npix / 1e6:.1f} Mpx) in {time.perf_counter() - t0:.1f} s")
+    from paper_2404_07780_amd import tune
+
+    t0 = time.perf_counter()
+    sched = tune.apply(gm, db, sample=args.tune_sample) if args.tune_sample > 0 else None
+    if sched:
+        log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']} "
+            f"(tuned in {time.perf_counter() - t0:.1f} s: {[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 1)) for t in sched['trials']]})")
     p = gm.p
     f_conv, f_red = flops_per_eval(b, p, p)    # planes: model + every non-sky variable
     f_eval = f_conv + f_red
@@ -320,6 +329,10 @@ def main():
                      "traffic_unit": "HBM bytes per launch", "kernel": head["kernel"], "kernel_ms": head["lm_ms"],
                      "flops_per_step": head["flops"]},
         "lm": {k: v for k, v in head.items() if k not in ("value", "ms_per_step", "achieved", "flops", "kernel")},
+        "schedule": (None if not sched else
+                     {"plane_groups": sched["plane_groups"], "wg_per_cu": sched["wg_per_cu"], "key": sched["key"],
+                      "trials_ms": {f"g{t['plane_groups']}w{t['wg_per_cu']}": t["ms"] for t in sched["trials"]},
+                      "sample": sched["sample"]}),
         "cpu_baseline": cpu,
         "parity": parity,
     }

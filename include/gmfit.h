@@ -122,6 +122,31 @@ int gm_model_image(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
 int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                 const double *params, float *jac_out, void *stream);
 
+/* Launch schedule of the fitting and error kernels (their workgroup shapes
+ * are fixed: 256 threads on 32 x 32 output tiles):
+ *   plane_groups -- how many groups the light and derivative planes of one
+ *     model evaluation are split into, each group evaluated and convolved in
+ *     one pass through LDS (fewer groups: less re-evaluation of the profile,
+ *     more LDS per workgroup); 0 = the library's default;
+ *   wg_per_cu -- persistent workgroups per compute unit, at most as many as
+ *     are resident; 0 = as many as are resident. */
+typedef struct {
+    int32_t plane_groups;
+    int32_t wg_per_cu;
+} gm_schedule;
+
+/* Use `sched` for models of the same family as `model` whose batches have
+ * PSF side psf_k (0: any side without a schedule of its own).  GM_EUNSUPPORTED
+ * if the family has no compiled variant with that many plane groups; a
+ * variant whose LDS does not fit a batch's PSF side falls back to the default. */
+int gm_set_schedule(gm_ctx *ctx, const gm_model *model, int32_t psf_k, const gm_schedule *sched);
+
+/* The plane-group counts compiled for the family of `model` that fit LDS at
+ * PSF side psf_k (odd), preferred first: up to cap into plane_groups_out, the
+ * total count into n_out.  Needs no device. */
+int gm_schedule_options(const gm_model *model, int32_t psf_k, int32_t *plane_groups_out, int32_t cap,
+                        int32_t *n_out);
+
 /* Adjoint of gm_model_image (the vector-Jacobian product used by gradient-based
  * fitters such as the paper's, Sec. 5.1): grad_params_out[g][c] =
  * sum over pixels of dM/dp_c (natural units, as gm_jacobian) times

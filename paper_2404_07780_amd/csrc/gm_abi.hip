@@ -155,15 +155,43 @@ void take(const gm_component &c, int s, int k, ModelArgs &ma)
     ma.fixedv[k] = c.fixed[s];
 }
 
-FamilyOps single_ops(int type)
+// Family tables (variants in order of preference), built once.
+enum { FAM_SERSIC = 1, FAM_EXPDISK, FAM_FERRER, FAM_KING, FAM_GAUSSIAN, FAM_MOFFAT, FAM_BULGEDISK, FAM_SERSICBAR };
+
+FamilyOps family(int id, Variant a, Variant b)
+{
+    FamilyOps f;
+    f.id = id;
+    f.n = 2;
+    f.v[0] = a;
+    f.v[1] = b;
+    return f;
+}
+
+const FamilyOps *family_table(int id)
+{
+    static const FamilyOps tab[] = {
+        family(FAM_SERSIC, var_sersic_1(), var_sersic_2()),
+        family(FAM_EXPDISK, var_expdisk_1(), var_expdisk_2()),
+        family(FAM_FERRER, var_ferrer_1(), var_ferrer_2()),
+        family(FAM_KING, var_king_1(), var_king_2()),
+        family(FAM_GAUSSIAN, var_gaussian_1(), var_gaussian_2()),
+        family(FAM_MOFFAT, var_moffat_1(), var_moffat_2()),
+        family(FAM_BULGEDISK, var_bulgedisk_2(), var_bulgedisk_3()),
+        family(FAM_SERSICBAR, var_sersicbar_2(), var_sersicbar_3()),
+    };
+    return &tab[id - 1];
+}
+
+const FamilyOps *single_ops(int type)
 {
     switch (type) {
-    case GM_SERSIC: return ops_sersic();
-    case GM_EXPDISK: return ops_expdisk();
-    case GM_FERRER: return ops_ferrer();
-    case GM_KING: return ops_king();
-    case GM_GAUSSIAN: return ops_gaussian();
-    default: return ops_moffat();
+    case GM_SERSIC: return family_table(FAM_SERSIC);
+    case GM_EXPDISK: return family_table(FAM_EXPDISK);
+    case GM_FERRER: return family_table(FAM_FERRER);
+    case GM_KING: return family_table(FAM_KING);
+    case GM_GAUSSIAN: return family_table(FAM_GAUSSIAN);
+    default: return family_table(FAM_MOFFAT);
     }
 }
 
@@ -216,7 +244,7 @@ int match_model(const gm_model *m, Match &out)
         if (rad[i]->param_index[2] >= 0) ma.nflux++;
     int nint;
     bool convolved = true;
-    FamilyOps ops;
+    const FamilyOps *ops;
     if (nrad == 1) {
         const gm_component &c = *rad[0];
         convolved = c.convolve != 0;
@@ -243,7 +271,7 @@ int match_model(const gm_model *m, Match &out)
         for (int s = nb; s < kSlots[b->type]; ++s) ma.cst[2 + s - nb] = b->fixed[s];
         nint = 7 + nb - 2 + 1;
         if (sky) take(*sky, 0, nint - 1, ma);
-        ops = b->type == GM_EXPDISK ? ops_bulgedisk() : ops_sersicbar();
+        ops = family_table(b->type == GM_EXPDISK ? FAM_BULGEDISK : FAM_SERSICBAR);
     }
     // a column used by two internal variables would be an unsupported tie
     std::vector<int> used(m->p, 0);
@@ -279,6 +307,33 @@ int prologue(gm_ctx *c, const gm_model *m, const gm_batch *b, Match &mt)
     if (rc) return rc;
     mt.ci.b = b;
     return GM_OK;
+}
+
+int pick_variant(gm_ctx *c, Match &mt, const Variant **out)
+{
+    const FamilyOps *f = mt.ops;
+    const int K = max_k(mt.ci);
+    // an explicit schedule for this PSF side, else one for every side
+    const gm_ctx::Sched *hit = nullptr;
+    for (const auto &e : c->sched)
+        if (e.family == f->id && (e.k == K || (e.k == 0 && !hit))) hit = &e;
+    mt.ci.wpc = 0;
+    if (hit) {
+        for (int i = 0; i < f->n; ++i)
+            if (f->v[i].ng == hit->ng || hit->ng == 0) {
+                if (f->v[i].lds(K) > kMaxLds) break;
+                mt.ci.wpc = hit->wpc;
+                *out = &f->v[i];
+                return GM_OK;
+            }
+    }
+    for (int i = 0; i < f->n; ++i)
+        if (f->v[i].lds(K) <= kMaxLds) {
+            if (hit) mt.ci.wpc = hit->wpc;
+            *out = &f->v[i];
+            return GM_OK;
+        }
+    return GM_EUNSUPPORTED;
 }
 
 }  // namespace gm
@@ -347,7 +402,9 @@ int gm_model_image(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     if (batch->n_gal == 0) return GM_OK;
     if (!params || !model_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.image(ctx, mt.ci, params, model_out, 0, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->image(ctx, mt.ci, params, model_out, 0, (hipStream_t)stream);
 }
 
 int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params, float *jac_out,
@@ -359,7 +416,51 @@ int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const
     if (batch->n_gal == 0) return GM_OK;
     if (!params || !jac_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.image(ctx, mt.ci, params, jac_out, 1, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->image(ctx, mt.ci, params, jac_out, 1, (hipStream_t)stream);
+}
+
+int gm_set_schedule(gm_ctx *ctx, const gm_model *model, int32_t psf_k, const gm_schedule *sched)
+{
+    if (!ctx || !sched || psf_k < 0 || (psf_k > 0 && (psf_k & 1) == 0) || sched->plane_groups < 0 ||
+        sched->wg_per_cu < 0)
+        return GM_EINVAL;
+    Match mt;
+    int rc = match_model(model, mt);
+    if (rc) return rc;
+    if (sched->plane_groups > 0) {
+        bool found = false;
+        for (int i = 0; i < mt.ops->n; ++i) found = found || mt.ops->v[i].ng == sched->plane_groups;
+        if (!found) return GM_EUNSUPPORTED;
+    }
+    const int k = mt.ci.convolved ? psf_k : 1;
+    for (auto &e : ctx->sched)
+        if (e.family == mt.ops->id && e.k == k) {
+            e.ng = sched->plane_groups;
+            e.wpc = sched->wg_per_cu;
+            return GM_OK;
+        }
+    ctx->sched.push_back({mt.ops->id, k, sched->plane_groups, sched->wg_per_cu});
+    return GM_OK;
+}
+
+int gm_schedule_options(const gm_model *model, int32_t psf_k, int32_t *plane_groups_out, int32_t cap,
+                        int32_t *n_out)
+{
+    if (!n_out || psf_k < 1 || (psf_k & 1) == 0 || cap < 0 || (cap > 0 && !plane_groups_out)) return GM_EINVAL;
+    Match mt;
+    int rc = match_model(model, mt);
+    if (rc) return rc;
+    const int k = mt.ci.convolved ? psf_k : 1;
+    int n = 0;
+    for (int i = 0; i < mt.ops->n; ++i)
+        if (mt.ops->v[i].lds(k) <= kMaxLds) {
+            if (n < cap) plane_groups_out[n] = mt.ops->v[i].ng;
+            ++n;
+        }
+    *n_out = n;
+    return GM_OK;
 }
 
 int gm_model_vjp(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params,
@@ -371,7 +472,9 @@ int gm_model_vjp(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     if (batch->n_gal == 0) return GM_OK;
     if (!params || !grad_image || !grad_params_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.vjp(ctx, mt.ci, params, grad_image, grad_params_out, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->vjp(ctx, mt.ci, params, grad_image, grad_params_out, (hipStream_t)stream);
 }
 
 int gm_default_guess(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, double *params_out,
@@ -383,7 +486,9 @@ int gm_default_guess(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, 
     if (batch->n_gal == 0) return GM_OK;
     if (!params_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.guess(ctx, mt.ci, params_out, moments_out, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->guess(ctx, mt.ci, params_out, moments_out, (hipStream_t)stream);
 }
 
 int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
@@ -396,7 +501,9 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     if (batch->n_gal == 0) return GM_OK;
     if (!params_inout || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, (hipStream_t)stream);
 }
 
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params,
@@ -408,7 +515,9 @@ int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, c
     if (batch->n_gal == 0) return GM_OK;
     if (!params || !err_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return mt.ops.errors(ctx, mt.ci, params, err_out, cov_out, (hipStream_t)stream);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->errors(ctx, mt.ci, params, err_out, cov_out, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -26,6 +26,10 @@ struct gm_ctx {
     size_t mlp_ws_bytes = 0;
     void *aux = nullptr;          // grow-only device scratch (adjoint partial sums)
     size_t aux_bytes = 0;
+    struct Sched {
+        int family, k, ng, wpc;
+    };
+    std::vector<Sched> sched;     // gm_set_schedule entries
 };
 
 namespace gm {
@@ -39,6 +43,7 @@ struct CallInfo {
     const gm_batch *b;
     ModelArgs ma;
     bool convolved;
+    int wpc = 0;          // persistent workgroups per CU (0: as many as are resident)
 };
 
 // Device workspace of one call: [meta | extra | queue counter].
@@ -90,24 +95,28 @@ int prepare(Kern kern, size_t lds, int *blocks_per_cu)
 }
 
 template <class F, int NG, int KT>
-int launch_fit(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArgs &fa, size_t lds, hipStream_t st)
+int launch_fit(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArgs &fa, size_t lds, int wpc,
+               hipStream_t st)
 {
     auto kern = lm_fit_kernel<F, KT, NG>;
     int per_cu;
     int rc = prepare(kern, lds, &per_cu);
     if (rc) return rc;
+    if (wpc > 0) per_cu = std::min(per_cu, wpc);
     int grid = std::min(fa.n_gal, per_cu * c->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, fa);
     return hip_rc(hipGetLastError());
 }
 
 template <class F, int NG, int KT>
-int launch_err(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, hipStream_t st)
+int launch_err(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, int wpc,
+               hipStream_t st)
 {
     auto kern = errors_kernel<F, KT, NG>;
     int per_cu;
     int rc = prepare(kern, lds, &per_cu);
     if (rc) return rc;
+    if (wpc > 0) per_cu = std::min(per_cu, wpc);
     int grid = std::min(ea.n_gal, per_cu * c->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, ea);
     return hip_rc(hipGetLastError());
@@ -191,7 +200,7 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     fa.max_iter = o ? o->max_iter : 100;
     fa.lambda0 = o ? o->lambda0 : 1e-3;
     fa.tol = o ? o->step_tol : 1e-4;
-    return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, st);
+    return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
 }
 
 template <class F, int NG, int... KTS>
@@ -204,7 +213,7 @@ int run_errors(gm_ctx *c, const CallInfo &ci, const double *params, double *err,
     rc = stage(c, ci, nullptr, 0, st, &sg);
     if (rc) return rc;
     ErrArgs ea{params, err, cov, ci.b->n_gal};
-    return Dispatch<F, NG, KTS...>::err(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ea, lds, st);
+    return Dispatch<F, NG, KTS...>::err(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), ea, lds, ci.wpc, st);
 }
 
 template <class F, int NG, int... KTS>
@@ -273,36 +282,68 @@ int run_guess(gm_ctx *c, const CallInfo &ci, double *params, double *moments, hi
     return hip_rc(hipGetLastError());
 }
 
-// Entry points of one family.
-struct FamilyOps {
+template <class F, int NG>
+size_t variant_lds(int K)
+{
+    return lds_bytes<F, NG>(K) + static_lds<F>();
+}
+
+// Entry points of one family compiled with NG plane groups.
+struct Variant {
+    int ng = 0;
+    size_t (*lds)(int K) = nullptr;     // LDS bytes per workgroup at PSF side K
     int (*fit)(gm_ctx *, const CallInfo &, const gm_fit_opts *, double *, double *, int32_t *, int32_t *,
-               hipStream_t);
-    int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t);
-    int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t);
-    int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t);
-    int (*vjp)(gm_ctx *, const CallInfo &, const double *, const float *, double *, hipStream_t);
+               hipStream_t) = nullptr;
+    int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t) = nullptr;
+    int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t) = nullptr;
+    int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t) = nullptr;
+    int (*vjp)(gm_ctx *, const CallInfo &, const double *, const float *, double *, hipStream_t) = nullptr;
 };
 
 template <class F, int NG, int... KTS>
-FamilyOps make_ops()
+Variant make_variant()
 {
-    return FamilyOps{run_fit<F, NG, KTS...>, run_errors<F, NG, KTS...>, run_image<F, NG, KTS...>, run_guess<F>,
-                     run_vjp<F, NG, KTS...>};
+    Variant v;
+    v.ng = NG;
+    v.lds = variant_lds<F, NG>;
+    v.fit = run_fit<F, NG, KTS...>;
+    v.errors = run_errors<F, NG, KTS...>;
+    v.image = run_image<F, NG, KTS...>;
+    v.guess = run_guess<F>;
+    v.vjp = run_vjp<F, NG, KTS...>;
+    return v;
 }
 
-// family tables, one per translation unit
-FamilyOps ops_sersic();
-FamilyOps ops_bulgedisk();
-FamilyOps ops_sersicbar();
-FamilyOps ops_expdisk();
-FamilyOps ops_ferrer();
-FamilyOps ops_king();
-FamilyOps ops_gaussian();
-FamilyOps ops_moffat();
+// A model family: its compiled variants in order of preference (the first
+// whose LDS fits is the default schedule).
+constexpr int kMaxVariants = 3;
+struct FamilyOps {
+    int id = 0;
+    int n = 0;
+    Variant v[kMaxVariants];
+};
+
+// variants, one per translation unit (gm_fam_*.hip)
+Variant var_sersic_1();
+Variant var_sersic_2();
+Variant var_bulgedisk_2();
+Variant var_bulgedisk_3();
+Variant var_sersicbar_2();
+Variant var_sersicbar_3();
+Variant var_expdisk_1();
+Variant var_expdisk_2();
+Variant var_ferrer_1();
+Variant var_ferrer_2();
+Variant var_king_1();
+Variant var_king_2();
+Variant var_gaussian_1();
+Variant var_gaussian_2();
+Variant var_moffat_1();
+Variant var_moffat_2();
 
 // A caller's gm_model matched against the compiled families (gm_abi.hip).
 struct Match {
-    FamilyOps ops{};
+    const FamilyOps *ops = nullptr;
     CallInfo ci{};
     int single_type = 0;      // profile type of a one-component model, else 0
     bool has_sky = false;
@@ -311,6 +352,9 @@ int match_model(const gm_model *m, Match &out);
 int check_batch(const gm_batch *b, bool convolved);
 // validate context, model and batch; fills mt (mt.ci.b = b)
 int prologue(gm_ctx *c, const gm_model *m, const gm_batch *b, Match &mt);
+// the variant a call runs with (context schedule, else the family default);
+// sets mt.ci.wpc.  GM_EUNSUPPORTED when no variant fits the batch's PSF side.
+int pick_variant(gm_ctx *c, Match &mt, const Variant **out);
 
 // makes the context's device current for the scope of a call
 struct Scoped {

@@ -895,8 +895,10 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     int *valid = cv.take<int>(n);
     int *active2 = cv.take<int>(n);
     int *nsave = cv.take<int>(n);
+    const Variant *var;
+    if ((rc = pick_variant(ctx, mt, &var))) return rc;
     // default guess (the fallback start), features, proposal
-    rc = mt.ops.guess(ctx, mt.ci, pdef, nullptr, st);
+    rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
     if (rc) return rc;
     rc = features_launch(ctx, mt, x, kInDim, mom8, st);
     if (rc) return rc;
@@ -913,7 +915,7 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr};
     o.active = valid;
     if ((rc = mark(0))) return rc;
-    rc = mt.ops.fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (rc) return rc;
     if ((rc = mark(1))) return rc;
     // invalid or unconverged: refit from the default guess
@@ -922,7 +924,7 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
     o.active = active2;
     if ((rc = mark(2))) return rc;
-    rc = mt.ops.fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (rc) return rc;
     if ((rc = mark(3))) return rc;
     hipLaunchKernelGGL(add_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nsave, niter_out);

@@ -24,7 +24,8 @@ SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
 
 # exported symbols (one per declaration of include/gmfit.h)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",
-           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_mlp_param_count", "gm_mlp_sync",
+           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_set_schedule",
+           "gm_schedule_options", "gm_mlp_param_count", "gm_mlp_sync",
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise")
 
@@ -54,6 +55,10 @@ class gm_batch(C.Structure):
 class gm_fit_opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double),
                 ("active", C.c_void_p)]
+
+
+class gm_schedule(C.Structure):
+    _fields_ = [("plane_groups", C.c_int32), ("wg_per_cu", C.c_int32)]
 
 
 class gm_mlp(C.Structure):
@@ -90,6 +95,8 @@ def lib() -> C.CDLL:
         L.gm_fit_batch.argtypes = [v, p, p, p, v, v, v, v, v]
         L.gm_param_errors.argtypes = [v, p, p, v, v, v, v]
         L.gm_model_vjp.argtypes = [v, p, p, v, v, v, v]
+        L.gm_set_schedule.argtypes = [v, p, i, p]
+        L.gm_schedule_options.argtypes = [p, i, v, i, v]
         i64, u64, f, d = C.c_int64, C.c_uint64, C.c_float, C.c_double
         L.gm_mlp_param_count.argtypes = [p]
         L.gm_mlp_param_count.restype = i64
@@ -104,7 +111,7 @@ def lib() -> C.CDLL:
         L.gm_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, v]
         L.gm_synth_noise.argtypes = [v, i, v, v, v, v, v, v, f, d, u64, i64, v, v, v, i, v]
         for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
-                     "gm_model_vjp", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
+                     "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise"):
             getattr(L, name).restype = i
@@ -273,6 +280,24 @@ def gm_jacobian(model: Model, batch: Batch, params, ctx: Optional[Context] = Non
     m, b = model.c(), batch.c()
     _check("gm_jacobian", lib().gm_jacobian(ctx.handle, C.byref(m), C.byref(b), _ptr(pr), _ptr(out), _stream()))
     return out
+
+
+def gm_set_schedule(model: Model, psf_k: int, plane_groups: int = 0, wg_per_cu: int = 0,
+                    ctx: Optional[Context] = None) -> None:
+    ctx = ctx or context()
+    m = model.c()
+    sc = gm_schedule(int(plane_groups), int(wg_per_cu))
+    _check("gm_set_schedule", lib().gm_set_schedule(ctx.handle, C.byref(m), int(psf_k), C.byref(sc)))
+
+
+def gm_schedule_options(model: Model, psf_k: int) -> List[int]:
+    """Compiled plane-group counts of the model's family that fit at PSF side
+    psf_k, preferred first."""
+    m = model.c()
+    buf = (C.c_int32 * 8)()
+    n = C.c_int32()
+    _check("gm_schedule_options", lib().gm_schedule_options(C.byref(m), int(psf_k), buf, 8, C.byref(n)))
+    return [int(buf[i]) for i in range(min(n.value, 8))]
 
 
 def gm_model_vjp(model: Model, batch: Batch, params, grad_image: torch.Tensor,

@@ -1,0 +1,113 @@
+"""Autotuner of the fitting kernels' launch schedule.
+
+For a model and a batch, every plane-group count compiled for the model's
+family (gm_schedule_options) is tried with the persistent grid at full
+residency and at one workgroup per CU: the LM fit from the moment start runs
+on a sample of the batch under each schedule (gm_set_schedule) and the
+fastest is kept.  Results are cached in a JSON file keyed by
+(device architecture, family, PSF side, parameter count, cutout-size bucket),
+so later runs apply a known schedule without timing.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import gmfit as G
+
+
+def family_key(model: G.Model) -> str:
+    parts = []
+    for c in model.comps:
+        parts.append(f"{c.type}{'c' if c.convolve else 'u'}")
+    return "+".join(parts)
+
+
+def size_bucket(batch: G.Batch) -> int:
+    """log2 of the mean cutout area, rounded."""
+    return int(round(math.log2(max(float(np.mean(batch.h.astype(np.float64) * batch.w)), 1.0))))
+
+
+def batch_psf_side(batch: G.Batch) -> int:
+    ks = np.unique(batch.psf_k)
+    return int(ks[0]) if len(ks) == 1 else 0
+
+
+def cache_key(model: G.Model, batch: G.Batch) -> str:
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    return f"{arch}|{family_key(model)}|K{batch_psf_side(batch)}|p{model.p}|a{size_bucket(batch)}"
+
+
+def subset(batch: G.Batch, n: int) -> G.Batch:
+    """The first n galaxies, sharing the device pixels (offsets unchanged)."""
+    n = min(n, batch.n)
+    return G.Batch(batch.h[:n], batch.w[:n], batch.img_off[:n], batch.psf_k[:n], batch.psf_off[:n], batch.data,
+                   batch.sigma, batch.psf, omega=batch.omega, device=batch.device)
+
+
+def _time_fit(model, sb, start, ctx, reps: int) -> float:
+    G.gm_fit_batch(model, sb, start, ctx=ctx)            # warm-up (kernel load, workspace growth)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        G.gm_fit_batch(model, sb, start, ctx=ctx)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune(model: G.Model, batch: G.Batch, sample: int = 2048, reps: int = 2,
+         ctx: Optional[G.Context] = None) -> Dict:
+    """Time every schedule on the first `sample` galaxies, apply the fastest and
+    return {"plane_groups", "wg_per_cu", "ms", "trials"}."""
+    ctx = ctx or G.context(batch.device.index)
+    k = batch_psf_side(batch)
+    sb = subset(batch, sample)
+    start, _ = G.gm_default_guess(model, sb, ctx=ctx)
+    trials = []
+    for ng in G.gm_schedule_options(model, k if k else int(batch.psf_k.max())):
+        for wpc in (0, 1):
+            G.gm_set_schedule(model, k, ng, wpc, ctx=ctx)
+            trials.append(dict(plane_groups=ng, wg_per_cu=wpc, ms=_time_fit(model, sb, start, ctx, reps)))
+    best = min(trials, key=lambda t: t["ms"])
+    G.gm_set_schedule(model, k, best["plane_groups"], best["wg_per_cu"], ctx=ctx)
+    return dict(best, trials=trials, sample=sb.n)
+
+
+def load(path: str) -> Dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save(path: str, cache: Dict) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply(model: G.Model, batch: G.Batch, cache_path: Optional[str] = None, sample: int = 2048,
+          ctx: Optional[G.Context] = None) -> Dict:
+    """Apply the cached schedule for this model and batch, tuning (and caching,
+    when a path is given) if there is none."""
+    ctx = ctx or G.context(batch.device.index)
+    key = cache_key(model, batch)
+    cache = load(cache_path) if cache_path else {}
+    if key in cache:
+        e = cache[key]
+        G.gm_set_schedule(model, batch_psf_side(batch), e["plane_groups"], e["wg_per_cu"], ctx=ctx)
+        return dict(e, key=key, cached=True)
+    res = tune(model, batch, sample=sample, ctx=ctx)
+    if cache_path:
+        cache[key] = {k: res[k] for k in ("plane_groups", "wg_per_cu", "ms")}
+        save(cache_path, cache)
+    return dict(res, key=key, cached=False)

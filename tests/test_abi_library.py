@@ -55,3 +55,13 @@ def test_error_strings(lib):
     assert lib.gm_error_string(0) == b"success"
     assert b"invalid" in lib.gm_error_string(-1)
     assert lib.gm_error_string(-99) == b"unknown error"
+
+
+def test_schedule_options_need_no_device():
+    from paper_2404_07780_amd import gmfit, synth
+
+    for name, want in (("sersic", {1, 2}), ("bulgedisk", {2, 3}), ("point", {1, 2})):
+        opts = gmfit.gm_schedule_options(gmfit.Model.from_spec(synth.MODEL_SPECS[name]), 25)
+        assert set(opts) == want, (name, opts)
+    with pytest.raises(gmfit.GmError):
+        gmfit.gm_schedule_options(gmfit.Model.from_spec(synth.MODEL_SPECS["sersic"]), 24)

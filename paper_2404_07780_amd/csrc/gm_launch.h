@@ -338,7 +338,6 @@ Variant var_king_1();
 Variant var_king_2();
 Variant var_gaussian_1();
 Variant var_gaussian_2();
-Variant var_moffat_1();
 Variant var_moffat_2();
 
 // A caller's gm_model matched against the compiled families (gm_abi.hip).

@@ -60,7 +60,9 @@ def test_error_strings(lib):
 def test_schedule_options_need_no_device():
     from paper_2404_07780_amd import gmfit, synth
 
-    for name, want in (("sersic", {1, 2}), ("bulgedisk", {2, 3}), ("point", {1, 2})):
+    # the Moffat family (point sources) has no one-plane-group variant: that variant gave wrong
+    # images and then a memory fault at PSF side 25, with no cause found in its source
+    for name, want in (("sersic", {1, 2}), ("bulgedisk", {2, 3}), ("point", {2}), ("king", {1, 2})):
         opts = gmfit.gm_schedule_options(gmfit.Model.from_spec(synth.MODEL_SPECS[name]), 25)
         assert set(opts) == want, (name, opts)
     with pytest.raises(gmfit.GmError):

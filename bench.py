@@ -134,9 +134,16 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None):
 
     def judge(gp, gs):
         both = (gs == 0) & (rs == 0)
-        npass = sum(int(param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))[0].all())
-                    for g in np.where(both)[0])
-        return dict(both_converged=int(both.sum()), pass_1e4=int(npass), gpu_converged=int((gs == 0).sum()))
+        npass, fails = 0, []
+        for g in np.where(both)[0]:
+            ok, worst = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
+            if ok.all():
+                npass += 1
+            else:
+                k = int(np.argmax(worst))
+                fails.append([int(g), names[k], round(float(worst[k]), 2), float(gp[g, k]), float(rp[g, k])])
+        return dict(both_converged=int(both.sum()), pass_1e4=int(npass), gpu_converged=int((gs == 0).sum()),
+                    fails=fails[:8])
 
     start, _ = G.gm_default_guess(gm, db)
     gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
@@ -206,7 +213,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=4096)
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="oracle sample size (0 = skip; default 1024 for the learned workload, else 48)")
+                    help="oracle sample size (0 = skip; default 2048 for the learned workload, else 48)")
     ap.add_argument("--tune-sample", type=int, default=2048,
                     help="galaxies timed per candidate schedule before the timed region (0 = library default)")
     ap.add_argument("--calib", action="store_true",
@@ -232,7 +239,7 @@ def main():
     seed = wl["seed"] if args.seed is None else args.seed
     learned = args.workload == "learned"
     if args.cpu_sample is None:
-        args.cpu_sample = 1024 if learned else 48
+        args.cpu_sample = 2048 if learned else 48
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()

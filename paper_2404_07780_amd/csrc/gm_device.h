@@ -611,14 +611,27 @@ struct Moffat {
 // ---------------------------------------------------------------- families
 // A family fixes, at compile time, the components of a model, the layout of
 // the internal LM vector u and the image planes: plane 0 is the summed light
-// of the components (FP64), plane 1 + k the derivative with respect to u_k
-// (FP32; sky, the last entry of u, has the constant derivative 1 and no plane).
+// of the components (FP64), plane plane(k) the derivative with respect to u_k
+// (FP32).  Two variables have no plane: sky (derivative 1) and DER, the
+// magnitude whose derivative follows from the light by linearity -- the light
+// of a component is proportional to 10^(-0.4 m), so d M / d m = -0.4 ln 10
+// times the component's convolved light (for the second component of a pair,
+// the total light minus the first component's share).  DER = -1 when the
+// flux parameter is an amplitude (dividing by it would fail at zero).
 
 // One component + sky: u = the component's slots, then sky.
 template <class C>
 struct FamSingle {
-    static constexpr int P = C::NS + 1, NPL = P, NCOMP = 1, NRAD = 1, SKY = C::NS, ND = C::NS;
+    static constexpr int P = C::NS + 1, NCOMP = 1, NRAD = 1, SKY = C::NS, ND = C::NS;
+    static constexpr int DER = C::kind(2) == KMAG ? 2 : -1;
+    static constexpr int NPL = DER >= 0 ? P - 1 : P;
     __host__ __device__ static constexpr int kind(int k) { return k < C::NS ? C::kind(k) : KSKY; }
+    __host__ __device__ static constexpr int plane(int k)
+    {
+        return (k == SKY || k == DER) ? -1 : (DER >= 0 && k > DER) ? k : k + 1;
+    }
+    // d M / d u_DER at a pixel from the convolved light acc0 and planes acc
+    __device__ static float derived(double acc0, const float *) { return kDMag * (float)acc0; }
     struct Prep {
         typename C::K k0;
         double sky;
@@ -639,7 +652,8 @@ struct FamSingle {
     __device__ static void scatter(int, const float *d, float *dp)
     {
 #pragma unroll
-        for (int i = 0; i < C::NS; ++i) dp[i] += d[i];
+        for (int i = 0; i < C::NS; ++i)
+            if (plane(i) > 0) dp[plane(i) - 1] += d[i];
     }
     __device__ static void default_guess(double xc, double yc, double m, double r0, double q0, double pa0,
                                          double sky0, double pk, double *nat)
@@ -660,8 +674,16 @@ struct FamSingle {
 template <class C1, class C2>
 struct FamPair {
     static constexpr int O2 = C1::NS - 2;                  // C2 slot s >= 2 sits at u[O2 + s]
-    static constexpr int P = C1::NS + C2::NS - 2 + 1, NPL = P, NCOMP = 2, NRAD = 2, SKY = P - 1;
+    static constexpr int P = C1::NS + C2::NS - 2 + 1, NCOMP = 2, NRAD = 2, SKY = P - 1;
     static constexpr int ND = C1::NS > C2::NS ? C1::NS : C2::NS;
+    // the second magnitude: d M / d m2 = -0.4 ln 10 M_light - d M / d m1
+    static constexpr int DER = (C1::kind(2) == KMAG && C2::kind(2) == KMAG) ? O2 + 2 : -1;
+    static constexpr int NPL = DER >= 0 ? P - 1 : P;
+    __host__ __device__ static constexpr int plane(int k)
+    {
+        return (k == SKY || k == DER) ? -1 : (DER >= 0 && k > DER) ? k : k + 1;
+    }
+    __device__ static float derived(double acc0, const float *acc) { return kDMag * (float)acc0 - acc[plane(2)]; }
     __host__ __device__ static constexpr int kind(int k)
     {
         return k < C1::NS ? C1::kind(k) : k < SKY ? C2::kind(k - O2) : KSKY;
@@ -693,12 +715,13 @@ struct FamPair {
     {
         if (c == 0) {
 #pragma unroll
-            for (int i = 0; i < C1::NS; ++i) dp[i] += d[i];
+            for (int i = 0; i < C1::NS; ++i) dp[plane(i) - 1] += d[i];
         } else {
-            dp[0] += d[0];
-            dp[1] += d[1];
+            dp[plane(0) - 1] += d[0];
+            dp[plane(1) - 1] += d[1];
 #pragma unroll
-            for (int i = 2; i < C2::NS; ++i) dp[O2 + i] += d[i];
+            for (int i = 2; i < C2::NS; ++i)
+                if (plane(O2 + i) > 0) dp[plane(O2 + i) - 1] += d[i];
         }
     }
     __device__ static void default_guess(double xc, double yc, double m, double r0, double q0, double pa0,

@@ -369,6 +369,20 @@ __device__ inline void tile_planes(const EvalShared<F> &sh, float *buf, int H, i
     }
 }
 
+// d M / d u_k at output column t of this thread's strip.
+template <class F>
+__device__ inline float jac_at(int k, int t, const double (&acc0)[4], const float (&acc)[F::NPL][4])
+{
+    if (k == F::SKY) return 1.0f;
+    if (k == F::DER) {
+        float col[F::NPL];
+#pragma unroll
+        for (int q = 0; q < F::NPL; ++q) col[q] = acc[q][t];
+        return F::derived(acc0[t], col);
+    }
+    return acc[F::plane(k)][t];
+}
+
 __device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
 {
     d = ba.data[idx];
@@ -420,12 +434,12 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
                     const float wr = wgt * (float)res;
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
-                        const float Jk = (k == F::SKY) ? 1.0f : acc[1 + k][t];
+                        const float Jk = jac_at<F>(k, t, acc0, acc);
                         red[k] = fmaf(wr, Jk, red[k]);
                         const float wj = wgt * Jk;
 #pragma unroll
                         for (int l = 0; l <= k; ++l) {
-                            const float Jl = (l == F::SKY) ? 1.0f : acc[1 + l][t];
+                            const float Jl = jac_at<F>(l, t, acc0, acc);
                             red[P + k * (k + 1) / 2 + l] = fmaf(wj, Jl, red[P + k * (k + 1) / 2 + l]);
                         }
                     }
@@ -893,13 +907,13 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
                         if (!sfree[k]) continue;
-                        float jv = (k == F::SKY) ? 1.0f : acc[1 + k][t];
+                        float jv = jac_at<F>(k, t, acc0, acc);
                         jo[(int64_t)ma.col[k] * H * W + pix] = jv * (float)sdu[k];
                     }
                 } else {
                     const double gw = (double)ia.gin[me.img_off + pix];
 #pragma unroll
-                    for (int k = 0; k < P; ++k) v[k] += (k == F::SKY ? 1.0 : (double)acc[1 + k][t]) * gw;
+                    for (int k = 0; k < P; ++k) v[k] += (double)jac_at<F>(k, t, acc0, acc) * gw;
                 }
             }
         }

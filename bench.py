@@ -254,9 +254,9 @@ def main():
         log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']} "
             f"(tuned in {time.perf_counter() - t0:.1f} s: {[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 1)) for t in sched['trials']]})")
     p = gm.p
-    # planes convolved per evaluation: the light and one per variable except sky and the
-    # magnitude whose derivative follows from the light (every workload here has one)
-    npl = p - 1
+    # planes convolved per evaluation: the light and one per variable except sky and, for
+    # one-component models, the magnitude whose derivative follows from the light
+    npl = p - 1 if len([c for c in gm.comps if c.type != S.SKY]) == 1 else p
     f_conv, f_red = flops_per_eval(b, p, npl)
     f_eval = f_conv + f_red
     ctx = G.context()

@@ -615,9 +615,11 @@ struct Moffat {
 // (FP32).  Two variables have no plane: sky (derivative 1) and DER, the
 // magnitude whose derivative follows from the light by linearity -- the light
 // of a component is proportional to 10^(-0.4 m), so d M / d m = -0.4 ln 10
-// times the component's convolved light (for the second component of a pair,
-// the total light minus the first component's share).  DER = -1 when the
-// flux parameter is an amplitude (dividing by it would fail at zero).
+// times the component's convolved light.  Only one-component families use it:
+// for a pair the second magnitude's derivative would be the total light minus
+// the first component's FP32 plane, which amplifies that plane's rounding by
+// the flux ratio of the components.  DER = -1 also when the flux parameter is
+// an amplitude (dividing by it would fail at zero).
 
 // One component + sky: u = the component's slots, then sky.
 template <class C>
@@ -676,14 +678,9 @@ struct FamPair {
     static constexpr int O2 = C1::NS - 2;                  // C2 slot s >= 2 sits at u[O2 + s]
     static constexpr int P = C1::NS + C2::NS - 2 + 1, NCOMP = 2, NRAD = 2, SKY = P - 1;
     static constexpr int ND = C1::NS > C2::NS ? C1::NS : C2::NS;
-    // the second magnitude: d M / d m2 = -0.4 ln 10 M_light - d M / d m1
-    static constexpr int DER = (C1::kind(2) == KMAG && C2::kind(2) == KMAG) ? O2 + 2 : -1;
-    static constexpr int NPL = DER >= 0 ? P - 1 : P;
-    __host__ __device__ static constexpr int plane(int k)
-    {
-        return (k == SKY || k == DER) ? -1 : (DER >= 0 && k > DER) ? k : k + 1;
-    }
-    __device__ static float derived(double acc0, const float *acc) { return kDMag * (float)acc0 - acc[plane(2)]; }
+    static constexpr int DER = -1, NPL = P;
+    __host__ __device__ static constexpr int plane(int k) { return k == SKY ? -1 : k + 1; }
+    __device__ static float derived(double, const float *) { return 0.0f; }
     __host__ __device__ static constexpr int kind(int k)
     {
         return k < C1::NS ? C1::kind(k) : k < SKY ? C2::kind(k - O2) : KSKY;

@@ -45,7 +45,10 @@ METRIC = "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs p
 # HBM bytes per LM-fit launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (scaled by the counts of a 1 GiB copy: FETCH x 2.0, WRITE x 1.0), keyed by
 # workload and the hash of the library sources they were taken with.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/lm_fit_learned65536.md: proposal + fallback LM launches of one learned step
+    "learned:65536:2:3f11adb5aebe5406": (1119650 + 29200) * 2.0 * 1024 + (10923 + 2306) * 1024,
+}
 
 
 def source_hash() -> str:

@@ -56,13 +56,38 @@ __device__ inline double digamma(double x)
     return s + log(x) - 0.5 / x - t;
 }
 
-// Butterfly sum over the 64 lanes of a wave; every lane gets the total, and
-// the order of additions is fixed.
+// Cross-lane moves of an FP64 value: a DPP row move (CTRL a compile-time
+// DPP control; lanes whose source falls outside the 16-lane row read 0) and
+// the value of one lane (wave-uniform lane index).  The whole wave must be
+// active.
+template <int CTRL>
+__device__ inline double dpp_move(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+__device__ inline double lane_value(double v, int lane)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane gets the total.  Within each
+// 16-lane row a shift-and-add ladder (row_shr 1, 2, 4, 8) leaves the row sum
+// in the row's last lane; the four row sums are then added in row order.
+// The order of additions is fixed, so results are reproducible.
 __device__ inline double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0x111>(v);
+    v += dpp_move<0x112>(v);
+    v += dpp_move<0x114>(v);
+    v += dpp_move<0x118>(v);
+    return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
 }
 
 // P(a, x) (regularised lower incomplete gamma) and dP/da, one wave: lane l

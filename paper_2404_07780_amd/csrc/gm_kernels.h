@@ -593,7 +593,6 @@ template <class F>
 struct LMShared {
     double u[F::P], ut[F::P], g[F::P], gt[F::P], A[F::P * F::P], At[F::P * F::P];
     double Dg[F::P], sig[F::P], delta[F::P];
-    double *M, *L, *inv;        // thread-0 temporaries in the (idle) plane buffer
     double chi2, chi2t, lambda;
     int freev[F::P];
     int t, status, fresh, apd, action;
@@ -613,97 +612,269 @@ struct FitArgs {
 
 enum { ACT_EVAL = 0, ACT_RETRY = 1, ACT_DONE = 2 };
 
-// Thread 0: choose the next trial point, or finish.
-template <class F>
-__device__ void lm_propose(LMShared<F> &s, const FitArgs &fa, int H, int W)
+// ---------------------------------------------------------------- wave-parallel LM step
+// One wave runs the LM bookkeeping between evaluations.  Lane r < P holds row
+// r of the P x P normal matrix; the Cholesky factorisation is row-parallel
+// (the pivot row is broadcast with readlane at every step), and the
+// triangular solves and the diagonal of the inverse are computed by every
+// lane from broadcast values.  Sums run in the same order as the textbook
+// one-thread algorithm.
+
+// L (lane r: row r) of M (lane r: row r); false if M is not positive definite.
+template <int P>
+__device__ inline bool chol_rows(const double (&m)[P], double (&l)[P], int lane)
 {
-    constexpr int P = F::P;
-    if (s.t >= fa.max_iter) {
-        s.status = GM_ST_MAXITER;
-        s.action = ACT_DONE;
-        return;
+#pragma unroll
+    for (int k = 0; k < P; ++k) l[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        double lj[P > 1 ? P - 1 : 1];
+#pragma unroll
+        for (int k = 0; k < j; ++k) lj[k] = lane_value(l[k], j);
+        double d = lane_value(m[j], j);
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= lj[k] * lj[k];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        const double ljj = sqrt(d);
+        double sr = m[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sr -= l[k] * lj[k];
+        l[j] = lane > j ? sr / ljj : (lane == j ? ljj : 0.0);
     }
-    s.t += 1;
-    if (s.fresh) {
-        double amax = 0.0;
-        for (int k = 0; k < P; ++k)
-            if (s.freev[k] && s.A[k * P + k] > amax) amax = s.A[k * P + k];
-        for (int k = 0; k < P; ++k) {
-            double d = s.A[k * P + k];
-            s.Dg[k] = s.freev[k] ? (d > 1e-12 * amax ? d : 1e-12 * amax) : 1.0;
-        }
-        s.apd = chol<P>(s.A, s.L);
-        if (s.apd) {
-            chol_inverse<P>(s.L, s.inv);
-            for (int k = 0; k < P; ++k) s.sig[k] = sqrt(s.inv[k * P + k]);
-            chol_solve<P>(s.L, s.g, s.delta);
-            double smax = 0.0;
-            for (int k = 0; k < P; ++k) {
-                double q = fabs(s.delta[k]) / s.sig[k];
-                if (!(q <= smax)) smax = q;
-            }
-            if (smax < fa.tol) {
-                s.t -= 1;
-                s.status = GM_ST_CONVERGED;
-                s.action = ACT_DONE;
-                return;
-            }
-        } else {
-            for (int k = 0; k < P; ++k) s.sig[k] = 1.0 / sqrt(s.Dg[k]);
-        }
-        s.fresh = 0;
+    return true;
+}
+
+// x = (L L^T)^-1 b, with b and the result as wave-uniform arrays.
+template <int P>
+__device__ inline void chol_solve_rows(const double (&l)[P], const double (&b)[P], double (&x)[P])
+{
+    double y[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        double t = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) t -= lane_value(l[k], i) * y[k];
+        y[i] = t / lane_value(l[i], i);
     }
-    for (int a = 0; a < P; ++a)
-        for (int b = 0; b < P; ++b) s.M[a * P + b] = s.A[a * P + b] + (a == b ? s.lambda * s.Dg[a] : 0.0);
-    if (!chol<P>(s.M, s.L)) {
-        s.lambda *= 10.0;
-        if (s.lambda > 1e9) {
-            s.status = GM_ST_STALLED;
-            s.action = ACT_DONE;
-        } else {
-            s.action = ACT_RETRY;
-        }
-        return;
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {
+        double t = y[i];
+#pragma unroll
+        for (int k = i + 1; k < P; ++k) t -= lane_value(l[i], k) * x[k];
+        x[i] = t / lane_value(l[i], i);
     }
-    chol_solve<P>(s.L, s.g, s.delta);
-    if (!s.apd) {
-        double smax = 0.0;
-        for (int k = 0; k < P; ++k) {
-            double q = fabs(s.delta[k]) / s.sig[k];
-            if (!(q <= smax)) smax = q;
+}
+
+// diag((L L^T)^-1)_c = sum_i (L^-1)_ic^2, as a wave-uniform array.
+template <int P>
+__device__ inline void chol_inv_diag_rows(const double (&l)[P], double (&dg)[P])
+{
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        double z[P];
+        double acc = 0.0;
+#pragma unroll
+        for (int i = c; i < P; ++i) {
+            double t = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = c; k < i; ++k) t -= lane_value(l[k], i) * z[k];
+            z[i] = t / lane_value(l[i], i);
+            acc += z[i] * z[i];
         }
-        if (smax < fa.tol) {
-            s.t -= 1;
-            s.status = GM_ST_CONVERGED;
-            s.action = ACT_DONE;
-            return;
-        }
+        dg[c] = acc;
     }
-    for (int k = 0; k < P; ++k) s.ut[k] = s.u[k] + (s.freev[k] ? s.delta[k] : 0.0);
-    clamp_u<F>(s.ut, H, W);
-    s.action = ACT_EVAL;
 }
 
 template <class F>
-__device__ void lm_accept(LMShared<F> &s)
+__device__ inline double clamp_var(int k, double v, int H, int W)
+{
+    const double big = 2.0 * (H > W ? H : W);
+    switch (F::kind(k)) {
+    case KX0: return fmin(fmax(v, 0.0), (double)W);
+    case KY0: return fmin(fmax(v, 0.0), (double)H);
+    case KSCALE: return fmin(fmax(v, log(0.1)), log(big));
+    case KN: return fmin(fmax(v, log(0.2)), log(10.0));
+    case KQ: return fmin(fmax(v, 0.05), 20.0);
+    default: return v;
+    }
+}
+
+// Wave 0, all lanes: absorb the evaluation just made (the start point, or a
+// trial: accept if chi^2 decreased, else raise the damping), then choose the
+// next trial point or finish.
+//   Start: A, g from the evaluation, fixed rows/columns replaced by the
+//     identity and their gradient by 0; lambda = lambda0.
+//   Stop test at every newly accepted state: the undamped Gauss-Newton step
+//     A^-1 g in units of sigma_k = sqrt([A^-1]_kk) below tol -> CONVERGED
+//     (while A is not positive definite: the damped step against
+//     1/sqrt(D_kk)).
+//   Trial: (A + lambda D) delta = g with D = diag(max(A_kk, 1e-12 max A_kk))
+//     of the current accepted A; a failed factorisation raises lambda by 10
+//     and counts the trial; lambda > 1e9 -> STALLED; max_iter trials ->
+//     MAXITER.
+template <class F>
+__device__ void lm_step_wave(LMShared<F> &s, const FitArgs &fa, int H, int W)
 {
     constexpr int P = F::P;
-    project_fixed<P>(s.freev, s.At, s.gt);
-    if (isfinite(s.chi2t) && s.chi2t < s.chi2) {
-        for (int k = 0; k < P; ++k) {
-            s.u[k] = s.ut[k];
-            s.g[k] = s.gt[k];
+    const int lane = threadIdx.x & 63;
+    const bool row = lane < P;
+    const int r = row ? lane : 0;
+    bool fv[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) fv[k] = s.freev[k] != 0;
+    bool fr = false;
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+        if (k == r) fr = fv[k];
+    int t = s.t, action = s.action, status = s.status, fresh = s.fresh, apd = s.apd;
+    double lambda = s.lambda, chi2 = s.chi2;
+    double a[P];
+    double gr, ur = s.u[r], dgr = s.Dg[r], sgr = s.sig[r];
+    bool newA = false, accepted = false;
+    if (t < 0 || action == ACT_EVAL) {
+        const double chi2t = s.chi2t;
+        const bool take = t < 0 || (isfinite(chi2t) && chi2t < chi2);
+        if (take) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) a[k] = (fr && fv[k]) ? s.At[r * P + k] : (r == k ? 1.0 : 0.0);
+            gr = fr ? s.gt[r] : 0.0;
+            newA = true;
+            chi2 = chi2t;
+            if (t < 0) {
+                t = 0;
+                if (!isfinite(chi2)) {
+                    status = GM_ST_NONFINITE;
+                    action = ACT_DONE;
+                }
+            } else {
+                accepted = true;
+                ur = s.ut[r];
+                lambda = fmax(lambda / 10.0, 1e-9);
+                fresh = 1;
+            }
+        } else {
+            lambda *= 10.0;
+            if (lambda > 1e9) {
+                status = GM_ST_STALLED;
+                action = ACT_DONE;
+            }
         }
-        for (int k = 0; k < P * P; ++k) s.A[k] = s.At[k];
-        s.chi2 = s.chi2t;
-        s.lambda = fmax(s.lambda / 10.0, 1e-9);
-        s.fresh = 1;
-    } else {
-        s.lambda *= 10.0;
-        if (s.lambda > 1e9) {
-            s.status = GM_ST_STALLED;
-            s.action = ACT_DONE;
+    }
+    if (!newA) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) a[k] = s.A[r * P + k];
+        gr = s.g[r];
+    }
+    double utr = ur;
+    bool proposed = false;
+    if (action != ACT_DONE) {
+        if (t >= fa.max_iter) {
+            status = GM_ST_MAXITER;
+            action = ACT_DONE;
+        } else {
+            t += 1;
+            double gv[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) gv[k] = lane_value(gr, k);
+            bool stop = false;
+            if (fresh) {
+                double drr = 0.0;
+#pragma unroll
+                for (int k = 0; k < P; ++k)
+                    if (k == r) drr = a[k];
+                double amax = 0.0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const double dk = lane_value(drr, k);
+                    if (fv[k] && dk > amax) amax = dk;
+                }
+                dgr = fr ? (drr > 1e-12 * amax ? drr : 1e-12 * amax) : 1.0;
+                double l[P];
+                apd = chol_rows<P>(a, l, lane) ? 1 : 0;
+                if (apd) {
+                    double idg[P], dv[P];
+                    chol_inv_diag_rows<P>(l, idg);
+                    chol_solve_rows<P>(l, gv, dv);
+                    double smax = 0.0;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        const double sk = sqrt(idg[k]);
+                        if (k == r) sgr = sk;
+                        const double q = fabs(dv[k]) / sk;
+                        if (!(q <= smax)) smax = q;
+                    }
+                    if (smax < fa.tol) {
+                        t -= 1;
+                        status = GM_ST_CONVERGED;
+                        action = ACT_DONE;
+                        stop = true;
+                    }
+                } else {
+                    sgr = 1.0 / sqrt(dgr);
+                }
+                fresh = 0;
+            }
+            if (!stop) {
+                double m[P], l[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) m[k] = a[k] + (k == r ? lambda * dgr : 0.0);
+                if (!chol_rows<P>(m, l, lane)) {
+                    lambda *= 10.0;
+                    if (lambda > 1e9) {
+                        status = GM_ST_STALLED;
+                        action = ACT_DONE;
+                    } else {
+                        action = ACT_RETRY;
+                    }
+                } else {
+                    double dv[P];
+                    chol_solve_rows<P>(l, gv, dv);
+                    bool conv = false;
+                    if (!apd) {
+                        double smax = 0.0;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            const double q = fabs(dv[k]) / lane_value(sgr, k);
+                            if (!(q <= smax)) smax = q;
+                        }
+                        conv = smax < fa.tol;
+                    }
+                    if (conv) {
+                        t -= 1;
+                        status = GM_ST_CONVERGED;
+                        action = ACT_DONE;
+                    } else {
+                        double dr = 0.0;
+#pragma unroll
+                        for (int k = 0; k < P; ++k)
+                            if (k == r) dr = dv[k];
+                        utr = clamp_var<F>(r, ur + (fr ? dr : 0.0), H, W);
+                        proposed = true;
+                        action = ACT_EVAL;
+                    }
+                }
+            }
         }
+    }
+    if (row) {
+        if (newA) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) s.A[r * P + k] = a[k];
+            s.g[r] = gr;
+        }
+        if (accepted) s.u[r] = ur;
+        if (proposed) s.ut[r] = utr;
+        s.Dg[r] = dgr;
+        s.sig[r] = sgr;
+    }
+    if (lane == 0) {
+        s.t = t;
+        s.action = action;
+        s.status = status;
+        s.fresh = fresh;
+        s.apd = apd;
+        s.lambda = lambda;
+        s.chi2 = chi2;
     }
 }
 
@@ -738,10 +909,6 @@ __global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, 
         }
         const Meta me = ba.meta[g];
         if (tid == 0) {
-            double *tmp = reinterpret_cast<double *>(planes);
-            s.M = tmp;
-            s.L = tmp + F::P * F::P;
-            s.inv = tmp + 2 * F::P * F::P;
             load_u<F>(s, ma, fa.params + (int64_t)g * ma.p);
             clamp_u<F>(s.u, me.h, me.w);
             for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
@@ -749,29 +916,20 @@ __global__ __launch_bounds__(NT) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, 
             s.status = GM_ST_MAXITER;
             s.lambda = fa.lambda0;
             s.fresh = 1;
+            s.apd = 0;
+            s.chi2 = 0.0;
             s.action = ACT_EVAL;
+            for (int k = 0; k < F::P; ++k) {
+                s.Dg[k] = 1.0;
+                s.sig[k] = 1.0;
+            }
         }
         __syncthreads();
         // one evaluation site: the start point first, then one trial per pass
         while (s.action != ACT_DONE) {
             if (s.action == ACT_EVAL)
                 evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
-            if (tid == 0) {
-                if (s.t < 0) {
-                    project_fixed<F::P>(s.freev, s.At, s.gt);
-                    for (int k = 0; k < F::P; ++k) s.g[k] = s.gt[k];
-                    for (int k = 0; k < F::P * F::P; ++k) s.A[k] = s.At[k];
-                    s.chi2 = s.chi2t;
-                    s.t = 0;
-                    if (!isfinite(s.chi2)) {
-                        s.status = GM_ST_NONFINITE;
-                        s.action = ACT_DONE;
-                    }
-                } else if (s.action == ACT_EVAL) {
-                    lm_accept<F>(s);
-                }
-                if (s.action != ACT_DONE) lm_propose<F>(s, fa, me.h, me.w);
-            }
+            if (tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
             __syncthreads();
         }
         if (tid == 0) {
@@ -810,25 +968,25 @@ __global__ __launch_bounds__(NT) void errors_kernel(ModelArgs ma, BatchArgs ba, 
         __syncthreads();
         evaluate<F, KT, NG>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
         if (tid == 0) {
-            double *tmp = reinterpret_cast<double *>(planes);
-            s.L = tmp;
-            s.inv = tmp + P * P;
+            // thread-0 temporaries in the idle plane buffer
+            double *L = reinterpret_cast<double *>(planes);
+            double *inv = L + P * P;
             project_fixed<P>(s.freev, s.A, s.g);
             const int p = ma.p;
             double *err = ea.err + (int64_t)g * p;
             double *cov = ea.cov ? ea.cov + (int64_t)g * p * p : nullptr;
-            if (chol<P>(s.A, s.L)) {
-                chol_inverse<P>(s.L, s.inv);
+            if (chol<P>(s.A, L)) {
+                chol_inverse<P>(L, inv);
                 for (int a = 0; a < P; ++a) {
                     if (ma.col[a] < 0) continue;
                     double na = u_to_nat(F::kind(a), s.u[a]);
                     double sa = dnat_du(F::kind(a), na);
-                    err[ma.col[a]] = sqrt(s.inv[a * P + a]) * fabs(sa);
+                    err[ma.col[a]] = sqrt(inv[a * P + a]) * fabs(sa);
                     if (cov)
                         for (int b = 0; b < P; ++b) {
                             if (ma.col[b] < 0) continue;
                             double nb = u_to_nat(F::kind(b), s.u[b]);
-                            cov[ma.col[a] * p + ma.col[b]] = sa * s.inv[a * P + b] * dnat_du(F::kind(b), nb);
+                            cov[ma.col[a] * p + ma.col[b]] = sa * inv[a * P + b] * dnat_du(F::kind(b), nb);
                         }
                 }
             } else {

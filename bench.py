@@ -306,6 +306,12 @@ def main():
             extra = dict(guess_ms=float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)])),
                          errors_ms=float(np.mean([evs[i][2].elapsed_time(evs[i][3]) for i in range(args.steps)])))
             kernel = "lm_fit_kernel"
+        conv = st == G.ST_CONVERGED
+        if name == "learned":
+            conv = conv & (fb == 0)
+        pct = np.percentile(nit[conv], [50, 90, 99, 99.9]).tolist() if conv.any() else []
+        extra["iters_converged_p50_p90_p99_p999_max"] = [round(v, 1) for v in pct] + (
+            [float(nit[conv].max())] if conv.any() else [])
         evals = evals * (st != G.ST_NONFINITE)
         flops = float(np.sum(f_eval * evals))
         lm_s = float(np.mean(lm_ms)) / 1e3

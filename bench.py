@@ -115,7 +115,7 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
     return 2.0 * hw * k2 * npl, 2.0 * hw * (p * (p + 1) / 2 + p + 1)
 
 
-def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None):
+def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 50):
     """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
     noised on the host), all host cores, LM from its own moment start; the GPU
     fits of the same data (plain, and learned when a network is given) are
@@ -153,7 +153,7 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None):
     parity = dict(sample=n_sample, oracle_converged=int((rs == 0).sum()), oracle_mean_iters=float(rn.mean()),
                   plain=judge(gp, gs))
     if mlp is not None:
-        lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp)]
+        lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=pmi)]
         parity["learned"] = judge(lp, ls)
         parity["learned"]["fallback"] = int((fb != 0).sum())
     cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--train-n", type=int, default=1 << 20, help="training galaxies (learned workload)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=4096)
+    ap.add_argument("--proposal-max-iter", type=int, default=50,
+                    help="LM trials from the learned start before the moment-start fallback")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="oracle sample size (0 = skip; default 2048 for the learned workload, else 48)")
     ap.add_argument("--tune-sample", type=int, default=2048,
@@ -285,7 +287,8 @@ def main():
             ev[3].record(stream)
 
     def learned_step(ev):
-        G.gm_fit_learned(gm, db, mlp, ctx=ctx, out=(params, chi2, niter, status, fallback), events=ev)
+        G.gm_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter, ctx=ctx,
+                         out=(params, chi2, niter, status, fallback), events=ev)
         G.gm_param_errors(gm, db, params, ctx=ctx)
 
     results = {}
@@ -324,7 +327,7 @@ def main():
     cpu, parity = None, None
     if args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} galaxies")
-        cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp)
+        cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp, args.proposal_max_iter)
 
     key = f"{args.workload}:{n}:{seed}:{source_hash()}"
     out = {
@@ -342,7 +345,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "n_gal": n, "seed": seed,
                    "init": "learned proposal + moment fallback" if learned else "moment-based",
-                   "max_iter": 100, "step_tol": 1e-4},
+                   "max_iter": 100, "step_tol": 1e-4,
+                   **({"proposal_max_iter": args.proposal_max_iter} if learned else {})},
         "roofline": {"bound": "alu", "achieved": head["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": head["achieved"] / PEAK_FP32_TFLOPS, "traffic": TRAFFIC.get(key),
                      "traffic_unit": "HBM bytes per launch", "kernel": head["kernel"], "kernel_ms": head["lm_ms"],

@@ -98,6 +98,8 @@ typedef struct {
     double step_tol;          /* stop when max_k |GN step_k| / sigma_k < step_tol (1e-4) */
     const int32_t *active;    /* DEVICE [n_gal] or NULL: galaxies with active[g] == 0 are
                                  skipped and their outputs left untouched */
+    int32_t proposal_max_iter;  /* gm_fit_learned: trials of the LM from the learned start
+                                   before the fallback (0 = max_iter) */
 } gm_fit_opts;
 
 typedef struct gm_ctx gm_ctx;
@@ -272,7 +274,8 @@ int gm_proposal_decode(gm_ctx *ctx, const gm_model *model, const gm_batch *batch
 
 /* LM from the network's proposal with the moment-based guess as fallback:
  * galaxies whose proposal is invalid, or whose LM from it does not end
- * GM_ST_CONVERGED, are refitted from gm_default_guess; their reported result
+ * GM_ST_CONVERGED within opts->proposal_max_iter trials, are refitted from
+ * gm_default_guess (with opts->max_iter trials); their reported result
  * is the refit and niter_out counts the trials of both fits.  fallback_out
  * (device, nullable) [n_gal]: 0 = fitted from the proposal, 1 = proposal
  * invalid, 2 = LM from the proposal did not converge (refitted).

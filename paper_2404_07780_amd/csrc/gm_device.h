@@ -93,7 +93,10 @@ __device__ inline double wave_sum(double v)
 // P(a, x) (regularised lower incomplete gamma) and dP/da, one wave: lane l
 // sums the terms k = l, l + 64, l + 128 of the series P = sum_k T_k,
 // T_k = e^-x x^(a+k) / Gamma(a+k+1), dT_k/da = T_k (ln x - psi(a+k+1)).
-// 192 terms cover x <= a + 20 for a <= 20 to double precision.
+// 192 terms cover x <= a + 20 for a <= 20 to double precision; a block of 64
+// terms is skipped once the last term of the previous block is below 1e-17
+// of the sum and the ratio of successive terms, x / (a + k), is below 1/2
+// (the rest of the series is then below twice that last term).
 __device__ inline void gammainc_wave(double a, double x, int lane, bool want_da, double *P, double *dPda)
 {
     double lx = log(x), sp = 0.0, sd = 0.0;
@@ -103,6 +106,7 @@ __device__ inline void gammainc_wave(double a, double x, int lane, bool want_da,
         double T = exp((a + k) * lx - x - lgamma(a + k + 1.0));
         sp += T;
         if (want_da) sd += T * (lx - digamma(a + k + 1.0));
+        if (m < 2 && x < 0.5 * (a + 64.0 * (m + 1)) && lane_value(T, 63) < 1e-17 * wave_sum(sp)) break;
     }
     *P = wave_sum(sp);
     if (want_da) *dPda = wave_sum(sd);
@@ -110,8 +114,11 @@ __device__ inline void gammainc_wave(double a, double x, int lane, bool want_da,
 
 // nu_n of the Sersic law (the b_n of Sec. 4.1): the root of P(2n, b) = 1/2,
 // the half-light condition; Newton from the asymptotic expansion of
-// Ciotti & Bertin (1999), safeguarded by a bisection bracket; db/dn by
-// implicit differentiation, -2 (dP/da) / (dP/dx).  All lanes of one wave.
+// Ciotti & Bertin (1999), safeguarded by a bisection bracket, stopped when
+// the error after a Newton step, about |f''/(2 f')| step^2 with
+// f''/f' = (a - 1)/b - 1, is below 1e-16 b (or a step is below 1e-14 b);
+// db/dn by implicit differentiation, -2 (dP/da) / (dP/dx).  All lanes of
+// one wave.
 __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
 {
     double a = 2.0 * n, lo = 0.0, hi = a + 20.0;
@@ -127,10 +134,12 @@ __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
         if (f > 0.0) hi = b; else lo = b;
         double fp = exp((a - 1.0) * log(b) - b - lga);
         double nb = b - f / fp;
-        if (!(nb > lo && nb < hi)) nb = 0.5 * (lo + hi);
+        const bool newton = nb > lo && nb < hi;
+        if (!newton) nb = 0.5 * (lo + hi);
         double st = fabs(nb - b);
+        const double pred = 0.5 * fabs((a - 1.0) / b - 1.0) * st * st;
         b = nb;
-        if (st < 1e-14 * b) break;
+        if (st < 1e-14 * b || (newton && pred < 1e-16 * b)) break;
     }
     double P, dPa;
     gammainc_wave(a, b, lane, true, &P, &dPa);

@@ -874,7 +874,9 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     if (rc) return rc;
     rc = check_proposal_mlp(mlp);
     if (rc) return rc;
-    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0))) return GM_EINVAL;
+    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0) ||
+                 opts->proposal_max_iter < 0))
+        return GM_EINVAL;
     if (batch->n_gal == 0) return GM_OK;
     if (!params_out || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
     Scoped sd(ctx->device);
@@ -912,7 +914,9 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
     auto mark = [&](int i) {
         return events && hipEventRecord((hipEvent_t)events[i], st) != hipSuccess ? GM_EHIP : GM_OK;
     };
-    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr};
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0};
+    const int full_iter = o.max_iter;
+    if (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) o.max_iter = o.proposal_max_iter;
     o.active = valid;
     if ((rc = mark(0))) return rc;
     rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
@@ -923,6 +927,7 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
                        params_out, active2, niter_out, nsave, fallback_out);
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
     o.active = active2;
+    o.max_iter = full_iter;
     if ((rc = mark(2))) return rc;
     rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (rc) return rc;

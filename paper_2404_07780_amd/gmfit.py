@@ -54,7 +54,7 @@ class gm_batch(C.Structure):
 
 class gm_fit_opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double),
-                ("active", C.c_void_p)]
+                ("active", C.c_void_p), ("proposal_max_iter", C.c_int32)]
 
 
 class gm_schedule(C.Structure):
@@ -341,7 +341,7 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
         params, chi2, niter, status = out
         if params0 is not None:
             params.copy_(_params_dev(params0, batch, model.p))
-    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr())
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr(), 0)
     m, b = model.c(), batch.c()
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
@@ -493,10 +493,12 @@ def gm_proposal_decode(model: Model, batch: Batch, out: torch.Tensor, moments: t
 
 
 def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, lambda0: float = 1e-3,
-                   step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None, events=None):
-    """(params, chi2, niter, status, fallback) as device tensors.  events: four
-    recorded torch.cuda.Event objects that the library re-records around its
-    two LM launches."""
+                   step_tol: float = 1e-4, proposal_max_iter: int = 50, ctx: Optional[Context] = None, out=None,
+                   events=None):
+    """(params, chi2, niter, status, fallback) as device tensors.  The LM from the
+    learned start gets proposal_max_iter trials (0: max_iter) before the
+    fallback.  events: four recorded torch.cuda.Event objects that the library
+    re-records around its two LM launches."""
     ctx = _ctx_for(batch.device, ctx)
     if out is None:
         params = torch.zeros(batch.n, model.p, dtype=torch.float64, device=batch.device)
@@ -506,7 +508,7 @@ def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, la
         fallback = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
     else:
         params, chi2, niter, status, fallback = out
-    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None)
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, int(proposal_max_iter))
     m, b, ml = model.c(), batch.c(), mlp.c()
     ev = None
     if events is not None:

@@ -262,3 +262,21 @@ def test_training_reduces_loss_and_iterations():
           f"parity {npass}/{nboth}", flush=True)
     assert ln.mean() < dn.mean()
     assert nboth >= 0.8 * b.n and npass >= 0.9 * nboth
+
+
+def test_proposal_trial_budget():
+    """With a budget of 2 trials from the learned start, slower fits go to the
+    fallback: their result is the moment-start fit and the trials add up."""
+    b = oracle_batch("sersic64", 24, seed=10)
+    gm = G.Model.from_spec(S.MODEL_SPECS["sersic"])
+    db = _dev(b)
+    mlp = G.MLP(np.zeros(M.param_count(), np.float32), train=False)
+    lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=2)]
+    start, _ = G.gm_default_guess(gm, db)
+    dp, dc, dn, ds = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    sel = fb == 2
+    print(f"budget 2: {int(sel.sum())} of {b.n} refitted", flush=True)
+    assert sel.sum() >= b.n // 2
+    assert np.array_equal(lp[sel], dp[sel]) and np.array_equal(ls[sel], ds[sel])
+    assert np.array_equal(ln[sel], dn[sel] + 2)
+    assert np.all(ls[fb == 0] == 0) and np.all(ln[fb == 0] <= 2)

@@ -64,7 +64,37 @@ __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x);
 
 // Input-region geometry of a tile for PSF side K (row pitch IWP in elements).
 __host__ __device__ inline int region_h(int K) { return TILE + K - 1; }
-__host__ __device__ inline int region_wp(int K) { return 28 + 4 * ((K + 3 + 3) / 4); }
+// Row pitch: at least the 32 outputs' 16-byte-aligned input segments
+// (28 + 4 ceil((K + 3) / 4) floats), padded to the next pitch that admits a
+// bank-disjoint pairing of rows (strip_gap below).
+__host__ __device__ inline int region_wp(int K)
+{
+    int w = 28 + 4 * ((K + 3 + 3) / 4);
+    while (!(w % 64 == 32 || w % 32 == 16 || w % 16 == 8)) w += 4;
+    return w;
+}
+
+// Output strip of thread tid in a tile: row r, columns 4 cg .. 4 cg + 3.  Wave
+// w covers rows 8w .. 8w + 7.  A 16-byte LDS read of a whole wave is served
+// 16 lanes at a time; the two 8-lane halves of such a group read rows GAP
+// apart, with GAP * IWP = 32 (mod 64) floats, so that the halves fall into
+// disjoint halves of the 64 banks (GAP 0: no such gap, rows in order).
+__host__ __device__ inline int strip_gap(int IWP)
+{
+    return (IWP % 64 == 32) ? 1 : (IWP % 32 == 16) ? 2 : (IWP % 16 == 8) ? 4 : 0;
+}
+__device__ inline void strip_of(int tid, int K, int &r, int &cg)
+{
+    const int lane = tid & 63, w = tid >> 6, gi = lane >> 4, h = (lane >> 3) & 1;
+    cg = lane & 7;
+    int rb;
+    switch (strip_gap(region_wp(K))) {
+    case 2: rb = (gi & 1) + 4 * (gi >> 1) + 2 * h; break;
+    case 4: rb = gi + 4 * h; break;
+    default: rb = lane >> 3; break;
+    }
+    r = 8 * w + rb;
+}
 
 // Plane groups: plane 0 (FP64) counts two units, the others one; groups are
 // contiguous and balanced in units.
@@ -411,7 +441,8 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     float red[NR - 1];
 #pragma unroll
     for (int q = 0; q < NR - 1; ++q) red[q] = 0.0f;
-    const int r = tid >> 3, cg = tid & 7;
+    int r, cg;
+    strip_of(tid, K, r, cg);
     const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
     for (int ty = 0; ty < nty; ++ty) {
         for (int tx = 0; tx < ntx; ++tx) {
@@ -1043,7 +1074,8 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
         __syncthreads();
         eval_prologue<F>(su, ma, H, W, esh, planes);
         const int ti0 = ti.ty * TILE, tj0 = ti.tx * TILE;
-        const int r = tid >> 3, cg = tid & 7;
+        int r, cg;
+        strip_of(tid, K, r, cg);
         double acc0[4];
         float acc[F::NPL][4];
         tile_planes<F, KT, NG>(esh, planes, H, W, K, ti0, tj0, (const cfloat *)(ba.psf + uniform64(me.psf_off)), r,

@@ -64,35 +64,25 @@ __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x);
 
 // Input-region geometry of a tile for PSF side K (row pitch IWP in elements).
 __host__ __device__ inline int region_h(int K) { return TILE + K - 1; }
-// Row pitch: at least the 32 outputs' 16-byte-aligned input segments
-// (28 + 4 ceil((K + 3) / 4) floats), padded to the next pitch that admits a
-// bank-disjoint pairing of rows (strip_gap below).
-__host__ __device__ inline int region_wp(int K)
-{
-    int w = 28 + 4 * ((K + 3 + 3) / 4);
-    while (!(w % 64 == 32 || w % 32 == 16 || w % 16 == 8)) w += 4;
-    return w;
-}
+// Row pitch: the 32 outputs' 16-byte-aligned input segments need
+// 28 + 4 ceil((K + 3) / 4) floats.
+__host__ __device__ inline int region_wp(int K) { return 28 + 4 * ((K + 3 + 3) / 4); }
 
 // Output strip of thread tid in a tile: row r, columns 4 cg .. 4 cg + 3.  Wave
-// w covers rows 8w .. 8w + 7.  A 16-byte LDS read of a whole wave is served
-// 16 lanes at a time; the two 8-lane halves of such a group read rows GAP
-// apart, with GAP * IWP = 32 (mod 64) floats, so that the halves fall into
-// disjoint halves of the 64 banks (GAP 0: no such gap, rows in order).
-__host__ __device__ inline int strip_gap(int IWP)
-{
-    return (IWP % 64 == 32) ? 1 : (IWP % 32 == 16) ? 2 : (IWP % 16 == 8) ? 4 : 0;
-}
+// w covers rows 8w .. 8w + 7, 8 lanes per row.  When the row pitch is 8
+// (mod 16) floats (PSF sides 7, 9, 23, 25, ...), adjacent rows' 16-byte
+// segment reads overlap on three quarters of the LDS banks; the two 8-lane
+// halves of each 16-lane group then take rows 4 apart (4 x pitch = 32 mod 64),
+// which measured 6% faster fits at K = 25.  Other pitches keep rows in order
+// (the paired mapping measured 1% slower at K = 15).
+__host__ __device__ inline int strip_gap(int IWP) { return (IWP % 16 == 8) ? 4 : 0; }
 __device__ inline void strip_of(int tid, int K, int &r, int &cg)
 {
     const int lane = tid & 63, w = tid >> 6, gi = lane >> 4, h = (lane >> 3) & 1;
     cg = lane & 7;
     int rb;
-    switch (strip_gap(region_wp(K))) {
-    case 2: rb = (gi & 1) + 4 * (gi >> 1) + 2 * h; break;
-    case 4: rb = gi + 4 * h; break;
-    default: rb = lane >> 3; break;
-    }
+    if (strip_gap(region_wp(K)) == 4) rb = gi + 4 * h;
+    else rb = lane >> 3;
     r = 8 * w + rb;
 }
 

@@ -47,7 +47,9 @@ METRIC = "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs p
 # workload and the hash of the library sources they were taken with.
 TRAFFIC = {
     # profiles/lm_fit_learned65536.md: proposal + fallback LM launches of one learned step
-    "learned:65536:2:3f11adb5aebe5406": (1119650 + 29200) * 2.0 * 1024 + (10923 + 2306) * 1024,
+    "learned:65536:2:1ac598db38566684": 2.387838e+09,
+    # profiles/lm_fit_uneven8192.md: one LM launch
+    "uneven:8192:0:1ac598db38566684": 1.321998e+10,
 }
 
 
@@ -218,7 +220,7 @@ def main():
     ap.add_argument("--proposal-max-iter", type=int, default=50,
                     help="LM trials from the learned start before the moment-start fallback")
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="oracle sample size (0 = skip; default 2048 for the learned workload, else 48)")
+                    help="oracle sample size (0 = skip; default: learned 2048, sersic64 64, others 160)")
     ap.add_argument("--tune-sample", type=int, default=2048,
                     help="galaxies timed per candidate schedule before the timed region (0 = library default)")
     ap.add_argument("--calib", action="store_true",
@@ -244,7 +246,7 @@ def main():
     seed = wl["seed"] if args.seed is None else args.seed
     learned = args.workload == "learned"
     if args.cpu_sample is None:
-        args.cpu_sample = 2048 if learned else 48
+        args.cpu_sample = {"learned": 2048, "sersic64": 64}.get(args.workload, 160)
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()

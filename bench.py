@@ -54,13 +54,15 @@ TRAFFIC = {
 
 
 def source_hash() -> str:
+    """Hash of the LM kernel's device code and launch drivers (the traffic
+    figures hold while it is unchanged)."""
     h = hashlib.sha256()
-    files = sorted(os.listdir(os.path.join(ROOT, "paper_2404_07780_amd", "csrc")))
+    csrc = os.path.join(ROOT, "paper_2404_07780_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc)
+                   if f in ("gm_kernels.h", "gm_device.h", "gm_launch.h") or f.startswith("gm_fam_"))
     for f in files:
-        with open(os.path.join(ROOT, "paper_2404_07780_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "gmfit.h"), "rb") as fh:
-        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -183,6 +185,26 @@ def timed(step, steps: int, warmup: int, name: str):
     return wall, evs
 
 
+def timed_plan(plan, steps: int, warmup: int, name: str):
+    """Replays of a captured plan; its four timing events are graph nodes,
+    read after each replay (the host waits for the last one before the next
+    launch)."""
+    for i in range(warmup):
+        plan.launch()
+        torch.cuda.synchronize()
+        log(f"{name}: warmup replay {i + 1}/{warmup} done")
+    seg = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plan.launch()
+        seg.append(plan.elapsed())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"{name}: timed {steps} replays in {wall:.3f} s")
+    return wall, seg
+
+
 def train_network(n_train: int, epochs: int, batch: int):
     from paper_2404_07780_amd import learned as Lrn
 
@@ -223,6 +245,8 @@ def main():
                     help="oracle sample size (0 = skip; default: learned 2048, sersic64 64, others 160)")
     ap.add_argument("--tune-sample", type=int, default=2048,
                     help="galaxies timed per candidate schedule before the timed region (0 = library default)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the eager calls instead of replays of the captured plans")
     ap.add_argument("--calib", action="store_true",
                     help="first run one 1 GiB device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -293,23 +317,47 @@ def main():
                          out=(params, chi2, niter, status, fallback), events=ev)
         G.gm_param_errors(gm, db, params, ctx=ctx)
 
+    names = ("learned", "plain") if learned else ("plain",)
+    plans = {}
+    if not args.eager:
+        t0 = time.perf_counter()
+        for name in names:
+            if name == "learned":
+                plans[name] = G.gm_plan_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter,
+                                                    errors=True, timing=True, ctx=ctx)
+            else:
+                plans[name] = G.gm_plan_fit(gm, db, start=None, errors=True, timing=True, ctx=ctx)
+        log(f"captured {len(plans)} plan(s) in {time.perf_counter() - t0:.2f} s")
+
     results = {}
-    for name, step in ((("learned", learned_step), ("plain", plain_step)) if learned else (("plain", plain_step),)):
-        wall, evs = timed(step, args.steps, args.warmup, name)
-        nit = niter.cpu().numpy().astype(np.float64)
-        st = status.cpu().numpy()
+    for name in names:
+        if args.eager:
+            wall, evs = timed(learned_step if name == "learned" else plain_step, args.steps, args.warmup, name)
+            if name == "learned":
+                seg = [[evs[i][0].elapsed_time(evs[i][1]), 0.0, evs[i][2].elapsed_time(evs[i][3])]
+                       for i in range(args.steps)]
+            else:
+                seg = [[evs[i][0].elapsed_time(evs[i][1]), evs[i][1].elapsed_time(evs[i][2]),
+                        evs[i][2].elapsed_time(evs[i][3])] for i in range(args.steps)]
+            out_t = (params, niter, status, fallback)
+        else:
+            plan = plans[name]
+            wall, seg = timed_plan(plan, args.steps, args.warmup, name)
+            out_t = (plan.params, plan.niter, plan.status, getattr(plan, "fallback", None))
+        nit = out_t[1].cpu().numpy().astype(np.float64)
+        st = out_t[2].cpu().numpy()
         if name == "learned":
-            fb = fallback.cpu().numpy()
-            lm_ms = [evs[i][0].elapsed_time(evs[i][1]) + evs[i][2].elapsed_time(evs[i][3])
-                     for i in range(args.steps)]
+            fb = out_t[3].cpu().numpy()
+            # events: before/after the LM from the proposals, before/after the fallback LM
+            lm_ms = [r[0] + r[2] for r in seg]
             evals = 1.0 + nit + (fb == 2)
             extra = dict(fallback_invalid=int((fb == 1).sum()), fallback_unconverged=int((fb == 2).sum()))
             kernel = "lm_fit_kernel (proposal launch + fallback launch)"
         else:
-            lm_ms = [evs[i][1].elapsed_time(evs[i][2]) for i in range(args.steps)]
+            # events: before the guess, before and after the LM, after the errors
+            lm_ms = [r[1] for r in seg]
             evals = 1.0 + nit
-            extra = dict(guess_ms=float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)])),
-                         errors_ms=float(np.mean([evs[i][2].elapsed_time(evs[i][3]) for i in range(args.steps)])))
+            extra = dict(guess_ms=float(np.mean([r[0] for r in seg])), errors_ms=float(np.mean([r[2] for r in seg])))
             kernel = "lm_fit_kernel"
         conv = st == G.ST_CONVERGED
         if name == "learned":
@@ -346,6 +394,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "n_gal": n, "seed": seed,
+                   "launch": "eager calls" if args.eager else "HIP graph replay of captured plans",
                    "init": "learned proposal + moment fallback" if learned else "moment-based",
                    "max_iter": 100, "step_tol": 1e-4,
                    **({"proposal_max_iter": args.proposal_max_iter} if learned else {})},

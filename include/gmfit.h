@@ -300,6 +300,53 @@ int gm_synth_noise(gm_ctx *ctx, int32_t n_gal, const int32_t *h, const int32_t *
                    float sigma, double m0, uint64_t seed, int64_t first_index, float *data_out,
                    float *sigma_out, double *mag_out, int32_t mag_stride, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Captured plans.  A plan records one call sequence on a fixed batch into a
+ * HIP graph: the host work of the calls (model matching, schedule choice,
+ * size metadata, the cost order of the work queue) is done once, at
+ * creation, into device memory the plan owns, and every gm_plan_launch
+ * replays only the kernels -- it allocates nothing and copies nothing from
+ * the host.  The plan keeps every device pointer it was given (pixels, PSFs,
+ * start vectors, network weights, outputs): the caller keeps those buffers
+ * alive until gm_plan_destroy and may change their contents between
+ * launches; the host size metadata is read at creation only.  A plan uses
+ * the schedule its context had at creation.  Launches of one plan must be
+ * ordered (one stream, or synchronised): they share the plan's workspace.
+ * The kernels and arithmetic are those of the eager calls, so a launch gives
+ * the same results bit for bit.  On failure *out is NULL and nothing stays
+ * allocated.  Creation synchronises with the device; n_gal must be >= 1.
+ * ---------------------------------------------------------------------- */
+typedef struct gm_plan gm_plan;
+
+/* params_out <- start (device [n_gal][p]; NULL: the moment-based guess of
+ * gm_default_guess), then gm_fit_batch, then (err_out not NULL)
+ * gm_param_errors at the fit.  timing != 0: the plan records four events of
+ * its own as graph nodes -- before the start, before and after the LM
+ * launch, at the end -- read with gm_plan_elapsed. */
+int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
+                const double *start, double *params_out, double *chi2_out, int32_t *niter_out,
+                int32_t *status_out, double *err_out, int32_t timing, gm_plan **out);
+
+/* gm_fit_learned, then (err_out not NULL) gm_param_errors at the fit.
+ * timing != 0: four events as those of gm_fit_learned (before and after the
+ * LM launch from the proposals, before and after the fallback LM launch),
+ * read with gm_plan_elapsed. */
+int gm_plan_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
+                        const gm_fit_opts *opts, double *params_out, double *chi2_out,
+                        int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,
+                        double *err_out, int32_t timing, gm_plan **out);
+
+/* Replays the plan on `stream` (asynchronous). */
+int gm_plan_launch(gm_plan *plan, void *stream);
+
+/* Milliseconds between the plan's consecutive timing events in its latest
+ * launch (ms_out[3]); waits for that launch's last event.  GM_EINVAL if the
+ * plan was made without timing or has not been launched. */
+int gm_plan_elapsed(gm_plan *plan, float *ms_out);
+
+/* Waits for the device, then frees the plan (NULL is ignored). */
+void gm_plan_destroy(gm_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

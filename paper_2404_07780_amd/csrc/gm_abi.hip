@@ -80,11 +80,24 @@ int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, 
     size_t mb_al = align256(sizeof(Meta) * (size_t)b->n_gal);
     size_t ex_al = align256(extra_bytes);
     size_t q_off = mb_al + ex_al;
-    int rc = ensure_host(c, mb_al + ex_al);
-    if (rc) return rc;
-    rc = ensure_dev(c, q_off + 256);
-    if (rc) return rc;
-    Meta *hm = reinterpret_cast<Meta *>(c->host);
+    char *hp, *dp;
+    gm_ctx::Capture *cap = c->capture;
+    if (cap) {
+        // plan capture: a fresh piece of the plan's arena, filled on the host now
+        // and uploaded after the capture
+        if (cap->used + q_off + 256 > cap->bytes) return GM_ENOMEM;
+        hp = cap->image.data() + cap->used;
+        dp = cap->arena + cap->used;
+        cap->used += q_off + 256;
+    } else {
+        int rc = ensure_host(c, mb_al + ex_al);
+        if (rc) return rc;
+        rc = ensure_dev(c, q_off + 256);
+        if (rc) return rc;
+        hp = reinterpret_cast<char *>(c->host);
+        dp = reinterpret_cast<char *>(c->dev);
+    }
+    Meta *hm = reinterpret_cast<Meta *>(hp);
     for (int g = 0; g < b->n_gal; ++g) {
         hm[g].h = b->h[g];
         hm[g].w = b->w[g];
@@ -93,15 +106,157 @@ int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, 
         hm[g].img_off = b->img_off[g];
         hm[g].psf_off = ci.convolved ? b->psf_off[g] : 0;
     }
-    char *hp = reinterpret_cast<char *>(c->host);
     if (extra_bytes) memcpy(hp + mb_al, extra, extra_bytes);
-    if (hipMemcpyAsync(c->dev, c->host, mb_al + ex_al, hipMemcpyHostToDevice, st) != hipSuccess) return GM_EHIP;
-    if (hipEventRecord(c->staged, st) != hipSuccess) return GM_EHIP;
-    c->pending = true;
-    char *dp = reinterpret_cast<char *>(c->dev);
+    if (!cap) {
+        if (hipMemcpyAsync(c->dev, c->host, mb_al + ex_al, hipMemcpyHostToDevice, st) != hipSuccess) return GM_EHIP;
+        if (hipEventRecord(c->staged, st) != hipSuccess) return GM_EHIP;
+        c->pending = true;
+    }
     out->meta = reinterpret_cast<Meta *>(dp);
     out->extra = dp + mb_al;
     out->queue = reinterpret_cast<int *>(dp + q_off);
+    return GM_OK;
+}
+
+int mark_event(const gm_ctx *c, void *const *events, int i, hipStream_t st)
+{
+    if (!events) return GM_OK;
+    if (!c->capture) return hip_rc(hipEventRecord((hipEvent_t)events[i], st));
+    // inside a capture: an event-record node after the nodes captured so far,
+    // made the stream's capture dependency so that later work follows it
+    hipStreamCaptureStatus cs;
+    unsigned long long id;
+    hipGraph_t g;
+    const hipGraphNode_t *deps;
+    size_t nd;
+    if (hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd) != hipSuccess ||
+        cs != hipStreamCaptureStatusActive)
+        return GM_EHIP;
+    hipGraphNode_t node;
+    if (hipGraphAddEventRecordNode(&node, g, deps, nd, (hipEvent_t)events[i]) != hipSuccess) return GM_EHIP;
+    return hip_rc(hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies));
+}
+
+int ctx_init(gm_ctx *c, int device)
+{
+    c->device = device;
+    hipDeviceProp_t prop;
+    const float one = 1.0f;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess ||
+        hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&c->unit_psf, sizeof(float)) != hipSuccess ||
+        hipMemcpy(c->unit_psf, &one, sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        ctx_release(c);
+        return GM_EHIP;
+    }
+    c->num_cu = prop.multiProcessorCount;
+    return GM_OK;
+}
+
+void ctx_release(gm_ctx *c)
+{
+    if (c->dev) (void)hipFree(c->dev);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->unit_psf) (void)hipFree(c->unit_psf);
+    if (c->mlp_ws) (void)hipFree(c->mlp_ws);
+    if (c->aux) (void)hipFree(c->aux);
+    if (c->staged) (void)hipEventDestroy(c->staged);
+    c->dev = c->host = c->mlp_ws = c->aux = nullptr;
+    c->unit_psf = nullptr;
+    c->staged = nullptr;
+    c->dev_bytes = c->host_bytes = c->mlp_ws_bytes = c->aux_bytes = 0;
+}
+
+namespace {
+
+void plan_free(gm_plan *p)
+{
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    if (p->cap.arena) (void)hipFree(p->cap.arena);
+    for (void *e : p->ev)
+        if (e) (void)hipEventDestroy((hipEvent_t)e);
+    ctx_release(&p->ctx);
+    delete p;
+}
+
+}  // namespace
+
+int plan_open(gm_ctx *parent, int n_gal, int stages, bool timing, gm_plan **out)
+{
+    *out = nullptr;
+    gm_plan *p = new (std::nothrow) gm_plan();
+    if (!p) return GM_ENOMEM;
+    int rc = ctx_init(&p->ctx, parent->device);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    p->ctx.sched = parent->sched;
+    // per staging: metadata, the largest extra a plan stages (the LPT order)
+    // and the queue counter
+    const size_t per = align256(sizeof(Meta) * (size_t)n_gal) + align256(sizeof(int) * (size_t)n_gal) + 256;
+    p->cap.bytes = per * (size_t)stages;
+    try {
+        p->cap.image.assign(p->cap.bytes, 0);
+    } catch (...) {
+        plan_free(p);
+        return GM_ENOMEM;
+    }
+    if (hipMalloc(&p->cap.arena, p->cap.bytes) != hipSuccess) {
+        p->cap.arena = nullptr;
+        plan_free(p);
+        return GM_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+        p->stream = nullptr;
+        plan_free(p);
+        return GM_EHIP;
+    }
+    for (int i = 0; timing && i < 4; ++i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            plan_free(p);
+            return GM_EHIP;
+        }
+        p->ev[i] = e;
+    }
+    *out = p;
+    return GM_OK;
+}
+
+int plan_begin(gm_plan *p)
+{
+    if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return GM_EHIP;
+    p->ctx.capture = &p->cap;
+    return GM_OK;
+}
+
+int plan_end(gm_plan *p, int rc, gm_plan **out)
+{
+    *out = nullptr;
+    if (p->ctx.capture) {
+        p->ctx.capture = nullptr;
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(p->stream, &g) != hipSuccess && rc == GM_OK) rc = GM_EHIP;
+        p->graph = g;
+        if (!g && rc == GM_OK) rc = GM_EHIP;
+    }
+    if (rc == GM_OK &&
+        hipMemcpy(p->cap.arena, p->cap.image.data(), p->cap.used, hipMemcpyHostToDevice) != hipSuccess)
+        rc = GM_EHIP;
+    if (rc == GM_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        p->exec = nullptr;
+        rc = GM_EHIP;
+    }
+    if (rc != GM_OK) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return rc;
+    }
+    *out = p;
     return GM_OK;
 }
 
@@ -349,6 +504,16 @@ int pick_variant(gm_ctx *c, Match &mt, const Variant **out)
 
 }  // namespace gm
 
+namespace {
+
+__global__ void copy_f64_kernel(const double *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
 extern "C" {
 
 int gm_create(gm_ctx **out, int hip_device)
@@ -361,19 +526,11 @@ int gm_create(gm_ctx **out, int hip_device)
     Scoped sd(hip_device);
     gm_ctx *c = new (std::nothrow) gm_ctx();
     if (!c) return GM_ENOMEM;
-    c->device = hip_device;
-    hipDeviceProp_t prop;
-    const float one = 1.0f;
-    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess ||
-        hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&c->unit_psf, sizeof(float)) != hipSuccess ||
-        hipMemcpy(c->unit_psf, &one, sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        if (c->unit_psf) (void)hipFree(c->unit_psf);
-        if (c->staged) (void)hipEventDestroy(c->staged);
+    int rc = ctx_init(c, hip_device);
+    if (rc) {
         delete c;
-        return GM_EHIP;
+        return rc;
     }
-    c->num_cu = prop.multiProcessorCount;
     *out = c;
     return GM_OK;
 }
@@ -383,12 +540,7 @@ void gm_destroy(gm_ctx *c)
     if (!c) return;
     Scoped sd(c->device);
     (void)hipDeviceSynchronize();
-    if (c->dev) (void)hipFree(c->dev);
-    if (c->host) (void)hipHostFree(c->host);
-    if (c->unit_psf) (void)hipFree(c->unit_psf);
-    if (c->mlp_ws) (void)hipFree(c->mlp_ws);
-    if (c->aux) (void)hipFree(c->aux);
-    if (c->staged) (void)hipEventDestroy(c->staged);
+    ctx_release(c);
     delete c;
 }
 
@@ -529,6 +681,72 @@ int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, c
     const Variant *v;
     if ((rc = pick_variant(ctx, mt, &v))) return rc;
     return v->errors(ctx, mt.ci, params, err_out, cov_out, (hipStream_t)stream);
+}
+
+int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
+                const double *start, double *params_out, double *chi2_out, int32_t *niter_out,
+                int32_t *status_out, double *err_out, int32_t timing, gm_plan **out)
+{
+    if (!out) return GM_EINVAL;
+    *out = nullptr;
+    Match mt;
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0))) return GM_EINVAL;
+    if (batch->n_gal == 0 || !params_out || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    gm_plan *p;
+    if ((rc = plan_open(ctx, batch->n_gal, 3, timing != 0, &p))) return rc;
+    gm_ctx *pc = &p->ctx;
+    void *const *events = timing ? p->ev : nullptr;
+    const hipStream_t st = p->stream;
+    const Variant *v = nullptr;
+    rc = pick_variant(pc, mt, &v);
+    if (!rc) rc = plan_begin(p);
+    if (!rc) rc = mark_event(pc, events, 0, st);
+    if (!rc) {
+        if (start) {
+            const int64_t cnt = (int64_t)batch->n_gal * model->p;
+            hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, start,
+                               params_out, cnt);
+            rc = hip_rc(hipGetLastError());
+        } else {
+            rc = v->guess(pc, mt.ci, params_out, nullptr, st);
+        }
+    }
+    if (!rc) rc = mark_event(pc, events, 1, st);
+    if (!rc) rc = v->fit(pc, mt.ci, opts, params_out, chi2_out, niter_out, status_out, st);
+    if (!rc) rc = mark_event(pc, events, 2, st);
+    if (!rc && err_out) rc = v->errors(pc, mt.ci, params_out, err_out, nullptr, st);
+    if (!rc) rc = mark_event(pc, events, 3, st);
+    return plan_end(p, rc, out);
+}
+
+int gm_plan_launch(gm_plan *plan, void *stream)
+{
+    if (!plan || !plan->exec) return GM_EINVAL;
+    Scoped sd(plan->ctx.device);
+    int rc = hip_rc(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    if (!rc) plan->launched = true;
+    return rc;
+}
+
+int gm_plan_elapsed(gm_plan *plan, float *ms_out)
+{
+    if (!plan || !ms_out || !plan->ev[0] || !plan->launched) return GM_EINVAL;
+    Scoped sd(plan->ctx.device);
+    hipEvent_t *e = reinterpret_cast<hipEvent_t *>(plan->ev);
+    if (hipEventSynchronize(e[3]) != hipSuccess) return GM_EHIP;
+    for (int i = 0; i < 3; ++i)
+        if (hipEventElapsedTime(&ms_out[i], e[i], e[i + 1]) != hipSuccess) return GM_EHIP;
+    return GM_OK;
+}
+
+void gm_plan_destroy(gm_plan *plan)
+{
+    if (!plan) return;
+    Scoped sd(plan->ctx.device);
+    plan_free(plan);
 }
 
 }  // extern "C"

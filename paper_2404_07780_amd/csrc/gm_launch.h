@@ -30,6 +30,29 @@ struct gm_ctx {
         int family, k, ng, wpc;
     };
     std::vector<Sched> sched;     // gm_set_schedule entries
+    // Set while a plan is being captured into a graph: staging then carves the
+    // plan's own device arena and writes the bytes to a host image of it,
+    // uploaded once the capture has ended (no copy or event enters the graph).
+    struct Capture {
+        char *arena = nullptr;
+        size_t bytes = 0;
+        size_t used = 0;
+        std::vector<char> image;
+    };
+    Capture *capture = nullptr;
+};
+
+// A captured call sequence (gm_plan_fit, gm_plan_fit_learned): a private
+// context whose workspaces only the graph's kernels use, the staging arena,
+// the capture stream and the instantiated graph.
+struct gm_plan {
+    gm_ctx ctx;
+    gm_ctx::Capture cap;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *ev[4] = {};       // timing events recorded as graph nodes (gm_plan_elapsed)
+    bool launched = false;
 };
 
 namespace gm {
@@ -59,6 +82,20 @@ int batch_kt(const CallInfo &ci);
 int max_k(const CallInfo &ci);
 // grow-only device scratch of the context (stream-ordered reuse)
 int ensure_aux(gm_ctx *c, size_t bytes, void **out);
+// context set-up and release (gm_create, gm_destroy and plans)
+int ctx_init(gm_ctx *c, int device);
+void ctx_release(gm_ctx *c);
+// records events[i] (if events is not null) on st; inside a capture as an
+// event node of the graph
+int mark_event(const gm_ctx *c, void *const *events, int i, hipStream_t st);
+// Plans: plan_open makes the private context (the parent's schedule copied),
+// an arena for `stages` stagings of n_gal galaxies and, when timing, the
+// plan's four events (p->ev, NULL otherwise); plan_begin starts the
+// capture on the plan's stream; plan_end ends it, uploads the arena and
+// instantiates the graph when rc is GM_OK, and on any failure destroys the plan.
+int plan_open(gm_ctx *parent, int n_gal, int stages, bool timing, gm_plan **out);
+int plan_begin(gm_plan *p);
+int plan_end(gm_plan *p, int rc, gm_plan **out);
 
 inline int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_EHIP; }
 

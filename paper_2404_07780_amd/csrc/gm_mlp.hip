@@ -738,6 +738,81 @@ int decode_launch(gm_ctx *c, const Match &mt, const float *out, int out_dim, con
     return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
 }
 
+
+int learned_checks(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
+                   const gm_fit_opts *opts, Match &mt)
+{
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if ((rc = check_proposal_model(mt))) return rc;
+    if ((rc = check_mlp(mlp, false))) return rc;
+    if ((rc = check_proposal_mlp(mlp))) return rc;
+    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0) ||
+                 opts->proposal_max_iter < 0))
+        return GM_EINVAL;
+    return GM_OK;
+}
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t learned_ws_bytes(const gm_mlp *mlp, int n, int p)
+{
+    return al256((size_t)n * kInDim * 2) + al256((size_t)n * 8 * 8) + al256((size_t)n * mlp->out_dim * 4) +
+           2 * al256((size_t)n * mlp->hidden * 2) + al256((size_t)n * p * 8) + 3 * al256((size_t)n * 4) + 256;
+}
+
+// The learned-start fit on the context's MLP workspace (already sized by
+// learned_ws_bytes): moment guess, features, network, decoding, LM from the
+// valid proposals, then LM from the moment guess where needed.
+int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *mlp, const gm_fit_opts *opts,
+                double *params_out, double *chi2_out, int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,
+                void *const *events, hipStream_t st)
+{
+    const int n = mt.ci.b->n_gal, p = mt.ci.ma.p;
+    Carve cv{reinterpret_cast<char *>(ctx->mlp_ws)};
+    uint16_t *x = cv.take<uint16_t>((size_t)n * kInDim);
+    double *mom8 = cv.take<double>((size_t)n * 8);
+    float *out = cv.take<float>((size_t)n * mlp->out_dim);
+    uint16_t *act0 = cv.take<uint16_t>((size_t)n * mlp->hidden);
+    uint16_t *act1 = cv.take<uint16_t>((size_t)n * mlp->hidden);
+    double *pdef = cv.take<double>((size_t)n * p);
+    int *valid = cv.take<int>(n);
+    int *active2 = cv.take<int>(n);
+    int *nsave = cv.take<int>(n);
+    // default guess (the fallback start), features, proposal
+    int rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
+    if (rc) return rc;
+    rc = features_launch(ctx, mt, x, kInDim, mom8, st);
+    if (rc) return rc;
+    uint16_t *Y[17];
+    for (int l = 0; l < mlp->n_hidden; ++l) Y[l] = (l & 1) ? act1 : act0;
+    rc = forward_pass(mlp, n, x, kInDim, nullptr, Y, nullptr, out, st);
+    if (rc) return rc;
+    rc = decode_launch(ctx, mt, out, mlp->out_dim, mom8, params_out, valid, st);
+    if (rc) return rc;
+    // LM from the valid proposals
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0};
+    const int full_iter = o.max_iter;
+    if (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) o.max_iter = o.proposal_max_iter;
+    o.active = valid;
+    if ((rc = mark_event(ctx, events, 0, st))) return rc;
+    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    if (rc) return rc;
+    if ((rc = mark_event(ctx, events, 1, st))) return rc;
+    // invalid or unconverged: refit from the default guess
+    hipLaunchKernelGGL(fallback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p, valid, status_out, pdef,
+                       params_out, active2, niter_out, nsave, fallback_out);
+    if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    o.active = active2;
+    o.max_iter = full_iter;
+    if ((rc = mark_event(ctx, events, 2, st))) return rc;
+    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    if (rc) return rc;
+    if ((rc = mark_event(ctx, events, 3, st))) return rc;
+    hipLaunchKernelGGL(add_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nsave, niter_out);
+    return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -866,74 +941,45 @@ int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, co
                    int32_t *status_out, int32_t *fallback_out, void *const *events, void *stream)
 {
     Match mt;
-    int rc = prologue(ctx, model, batch, mt);
+    int rc = learned_checks(ctx, model, batch, mlp, opts, mt);
     if (rc) return rc;
-    rc = check_proposal_model(mt);
-    if (rc) return rc;
-    rc = check_mlp(mlp, false);
-    if (rc) return rc;
-    rc = check_proposal_mlp(mlp);
-    if (rc) return rc;
-    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0) ||
-                 opts->proposal_max_iter < 0))
-        return GM_EINVAL;
     if (batch->n_gal == 0) return GM_OK;
     if (!params_out || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
     Scoped sd(ctx->device);
-    hipStream_t st = (hipStream_t)stream;
-    const int n = batch->n_gal, p = model->p;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t need = al((size_t)n * kInDim * 2) + al((size_t)n * 8 * 8) + al((size_t)n * mlp->out_dim * 4) +
-                        2 * al((size_t)n * mlp->hidden * 2) + al((size_t)n * p * 8) + 3 * al((size_t)n * 4) + 256;
-    rc = ensure_ws(ctx, need);
-    if (rc) return rc;
-    Carve cv{reinterpret_cast<char *>(ctx->mlp_ws)};
-    uint16_t *x = cv.take<uint16_t>((size_t)n * kInDim);
-    double *mom8 = cv.take<double>((size_t)n * 8);
-    float *out = cv.take<float>((size_t)n * mlp->out_dim);
-    uint16_t *act0 = cv.take<uint16_t>((size_t)n * mlp->hidden);
-    uint16_t *act1 = cv.take<uint16_t>((size_t)n * mlp->hidden);
-    double *pdef = cv.take<double>((size_t)n * p);
-    int *valid = cv.take<int>(n);
-    int *active2 = cv.take<int>(n);
-    int *nsave = cv.take<int>(n);
     const Variant *var;
     if ((rc = pick_variant(ctx, mt, &var))) return rc;
-    // default guess (the fallback start), features, proposal
-    rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
+    if ((rc = ensure_ws(ctx, learned_ws_bytes(mlp, batch->n_gal, model->p)))) return rc;
+    return learned_seq(ctx, mt, var, mlp, opts, params_out, chi2_out, niter_out, status_out, fallback_out, events,
+                       (hipStream_t)stream);
+}
+
+int gm_plan_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
+                        const gm_fit_opts *opts, double *params_out, double *chi2_out, int32_t *niter_out,
+                        int32_t *status_out, int32_t *fallback_out, double *err_out, int32_t timing,
+                        gm_plan **out)
+{
+    if (!out) return GM_EINVAL;
+    *out = nullptr;
+    Match mt;
+    int rc = learned_checks(ctx, model, batch, mlp, opts, mt);
     if (rc) return rc;
-    rc = features_launch(ctx, mt, x, kInDim, mom8, st);
-    if (rc) return rc;
-    uint16_t *Y[17];
-    for (int l = 0; l < mlp->n_hidden; ++l) Y[l] = (l & 1) ? act1 : act0;
-    rc = forward_pass(mlp, n, x, kInDim, nullptr, Y, nullptr, out, st);
-    if (rc) return rc;
-    rc = decode_launch(ctx, mt, out, mlp->out_dim, mom8, params_out, valid, st);
-    if (rc) return rc;
-    // LM from the valid proposals
-    auto mark = [&](int i) {
-        return events && hipEventRecord((hipEvent_t)events[i], st) != hipSuccess ? GM_EHIP : GM_OK;
-    };
-    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0};
-    const int full_iter = o.max_iter;
-    if (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) o.max_iter = o.proposal_max_iter;
-    o.active = valid;
-    if ((rc = mark(0))) return rc;
-    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
-    if (rc) return rc;
-    if ((rc = mark(1))) return rc;
-    // invalid or unconverged: refit from the default guess
-    hipLaunchKernelGGL(fallback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p, valid, status_out, pdef,
-                       params_out, active2, niter_out, nsave, fallback_out);
-    if (hipGetLastError() != hipSuccess) return GM_EHIP;
-    o.active = active2;
-    o.max_iter = full_iter;
-    if ((rc = mark(2))) return rc;
-    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
-    if (rc) return rc;
-    if ((rc = mark(3))) return rc;
-    hipLaunchKernelGGL(add_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nsave, niter_out);
-    return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
+    if (batch->n_gal == 0 || !params_out || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    gm_plan *p;
+    // stagings: guess, features, decode, two fits, errors
+    if ((rc = plan_open(ctx, batch->n_gal, 6, timing != 0, &p))) return rc;
+    gm_ctx *pc = &p->ctx;
+    void *const *events = timing ? p->ev : nullptr;
+    const Variant *var = nullptr;
+    rc = pick_variant(pc, mt, &var);
+    // the workspace is sized before the capture, which then allocates nothing
+    if (!rc) rc = ensure_ws(pc, learned_ws_bytes(mlp, batch->n_gal, model->p));
+    if (!rc) rc = plan_begin(p);
+    if (!rc)
+        rc = learned_seq(pc, mt, var, mlp, opts, params_out, chi2_out, niter_out, status_out, fallback_out, events,
+                         p->stream);
+    if (!rc && err_out) rc = var->errors(pc, mt.ci, params_out, err_out, nullptr, p->stream);
+    return plan_end(p, rc, out);
 }
 
 int gm_synth_noise(gm_ctx *ctx, int32_t n_gal, const int32_t *h, const int32_t *w, const int64_t *img_off,

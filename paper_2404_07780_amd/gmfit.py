@@ -27,7 +27,8 @@ SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_j
            "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_set_schedule",
            "gm_schedule_options", "gm_mlp_param_count", "gm_mlp_sync",
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
-           "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise")
+           "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise",
+           "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch", "gm_plan_elapsed", "gm_plan_destroy")
 
 
 class GmError(RuntimeError):
@@ -110,10 +111,17 @@ def lib() -> C.CDLL:
         L.gm_proposal_decode.argtypes = [v, p, p, v, i, v, v, v, v]
         L.gm_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, v]
         L.gm_synth_noise.argtypes = [v, i, v, v, v, v, v, v, f, d, u64, i64, v, v, v, i, v]
+        L.gm_plan_fit.argtypes = [v, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
+        L.gm_plan_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
+        L.gm_plan_launch.argtypes = [v, v]
+        L.gm_plan_elapsed.argtypes = [v, v]
+        L.gm_plan_destroy.argtypes = [v]
+        L.gm_plan_destroy.restype = None
         for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
-                     "gm_synth_noise"):
+                     "gm_synth_noise", "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch",
+                     "gm_plan_elapsed"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -510,15 +518,104 @@ def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, la
         params, chi2, niter, status, fallback = out
     o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, int(proposal_max_iter))
     m, b, ml = model.c(), batch.c(), mlp.c()
-    ev = None
-    if events is not None:
-        if len(events) != 4 or any(int(e.cuda_event) == 0 for e in events):
-            raise ValueError("events: four torch.cuda.Event objects, each recorded once")
-        ev = (C.c_void_p * 4)(*[int(e.cuda_event) for e in events])
+    ev = _events4(events)
     _check("gm_fit_learned", lib().gm_fit_learned(ctx.handle, C.byref(m), C.byref(b), C.byref(ml), C.byref(o),
                                                   _ptr(params), _ptr(chi2), _ptr(niter), _ptr(status),
                                                   _ptr(fallback), ev, _stream()))
     return params, chi2, niter, status, fallback
+
+
+def _events4(events):
+    if events is None:
+        return None
+    if len(events) != 4 or any(int(e.cuda_event) == 0 for e in events):
+        raise ValueError("events: four torch.cuda.Event objects, each recorded once")
+    return (C.c_void_p * 4)(*[int(e.cuda_event) for e in events])
+
+
+class Plan:
+    """A captured call sequence (gm_plan_fit / gm_plan_fit_learned): launch()
+    replays its graph on the current stream.  The plan holds the batch, the
+    inputs and its output tensors (attributes params, chi2, niter, status,
+    fallback, err) so that every pointer baked into the graph stays valid."""
+
+    def __init__(self, handle, device, keep, **outputs):
+        self._h = handle
+        self.device = device
+        self._keep = keep
+        for k, t in outputs.items():
+            setattr(self, k, t)
+
+    def launch(self) -> None:
+        if not self._h:
+            raise RuntimeError("plan destroyed")
+        _check("gm_plan_launch", lib().gm_plan_launch(self._h, _stream()))
+
+    def elapsed(self) -> List[float]:
+        """Milliseconds between the plan's four timing events in its latest
+        launch (waits for it); plans made with timing=True."""
+        ms = (C.c_float * 3)()
+        _check("gm_plan_elapsed", lib().gm_plan_elapsed(self._h, ms))
+        return [float(v) for v in ms]
+
+    def close(self) -> None:
+        if self._h:
+            lib().gm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _fit_outputs(model: Model, batch: Batch, errors: bool, fallback: bool):
+    dev = batch.device
+    out = dict(params=torch.zeros(batch.n, model.p, dtype=torch.float64, device=dev),
+               chi2=torch.empty(batch.n, dtype=torch.float64, device=dev),
+               niter=torch.empty(batch.n, dtype=torch.int32, device=dev),
+               status=torch.empty(batch.n, dtype=torch.int32, device=dev),
+               err=torch.empty(batch.n, model.p, dtype=torch.float64, device=dev) if errors else None)
+    if fallback:
+        out["fallback"] = torch.empty(batch.n, dtype=torch.int32, device=dev)
+    return out
+
+
+def gm_plan_fit(model: Model, batch: Batch, start=None, errors: bool = True, max_iter: int = 100,
+                lambda0: float = 1e-3, step_tol: float = 1e-4, active=None, timing: bool = False,
+                ctx: Optional[Context] = None) -> Plan:
+    """Capture start (None: the moment-based guess) -> LM -> (errors) on this
+    batch.  Each launch() refits from `start`: a contiguous float64 device
+    tensor [n, p] is used in place (its contents may change between
+    launches); anything else is copied once."""
+    ctx = _ctx_for(batch.device, ctx)
+    st = None if start is None else _params_dev(start, batch, model.p).contiguous()
+    out = _fit_outputs(model, batch, errors, False)
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr(), 0)
+    m, b = model.c(), batch.c()
+    h = C.c_void_p()
+    _check("gm_plan_fit", lib().gm_plan_fit(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(st),
+                                            _ptr(out["params"]), _ptr(out["chi2"]), _ptr(out["niter"]),
+                                            _ptr(out["status"]), _ptr(out["err"]), int(bool(timing)), C.byref(h)))
+    return Plan(h, batch.device, (ctx, batch, st, active), **out)
+
+
+def gm_plan_fit_learned(model: Model, batch: Batch, mlp: "MLP", errors: bool = True, max_iter: int = 100,
+                        lambda0: float = 1e-3, step_tol: float = 1e-4, proposal_max_iter: int = 50,
+                        timing: bool = False, ctx: Optional[Context] = None) -> Plan:
+    """Capture gm_fit_learned -> (errors) on this batch; the network's weights
+    are read at each launch."""
+    ctx = _ctx_for(batch.device, ctx)
+    out = _fit_outputs(model, batch, errors, True)
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, int(proposal_max_iter))
+    m, b, ml = model.c(), batch.c(), mlp.c()
+    h = C.c_void_p()
+    _check("gm_plan_fit_learned",
+           lib().gm_plan_fit_learned(ctx.handle, C.byref(m), C.byref(b), C.byref(ml), C.byref(o), _ptr(out["params"]),
+                                     _ptr(out["chi2"]), _ptr(out["niter"]), _ptr(out["status"]),
+                                     _ptr(out["fallback"]), _ptr(out["err"]), int(bool(timing)), C.byref(h)))
+    return Plan(h, batch.device, (ctx, batch, mlp), **out)
 
 
 def gm_synth_noise(h, w, img_off, unit: torch.Tensor, snr: torch.Tensor, sky: torch.Tensor, sigma: float,

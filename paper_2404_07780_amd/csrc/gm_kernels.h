@@ -223,33 +223,46 @@ __device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, d
 
 // Fill the LDS planes LO..HI-1 of the input region of the tile at (ti0, tj0).
 // Layout: if LO == 0 the FP64 light plane comes first (two float units),
-// then the FP32 planes in order.
+// then the FP32 planes in order.  Region points outside the image are the
+// convolution's zero padding; the points inside form a rectangle whose
+// profile values are spread linearly over all threads of the workgroup.
 template <class F, int LO, int HI>
 __device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, int K, int ti0, int tj0)
 {
     const int IH = region_h(K), IWP = region_wp(K), IW = TILE + K - 1, c = (K - 1) / 2;
     const int plane_sz = IH * IWP;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *b0 = reinterpret_cast<double *>(buf);
     float *bf = (LO == 0) ? buf + 2 * plane_sz : buf;
     constexpr int QLO = LO == 0 ? 1 : LO;
-    for (int ri = wave; ri < IH; ri += NWAVE) {
-        const int i = ti0 - c + ri;
-        for (int ci = lane; ci < IWP; ci += 64) {
-            const int j = tj0 - c + ci;
-            double v0 = 0.0;
-            float dp[F::NPL - 1];
-            if (ci < IW && i >= 0 && i < H && j >= 0 && j < W) {
-                planes_at<F, LO == 0>(sh, i, j, H, v0, dp);
-            } else {
+    // region rows r0..r1-1 and columns c0..c1-1 lie inside the image
+    const int r0 = max(0, c - ti0), r1 = min(IH, H + c - ti0);
+    const int c0 = max(0, c - tj0), c1 = min(IW, W + c - tj0);
+    auto store = [&](int idx, double v0, const float *dp) {
+        if constexpr (LO == 0) b0[idx] = v0;
 #pragma unroll
-                for (int q = 0; q < F::NPL - 1; ++q) dp[q] = 0.0f;
-            }
-            const int idx = ri * IWP + ci;
-            if constexpr (LO == 0) b0[idx] = v0;
+        for (int q = QLO; q < HI; ++q) bf[(q - QLO) * plane_sz + idx] = dp[q - 1];
+    };
+    const bool edge = r0 > 0 || r1 < IH || c0 > 0 || c1 < IW;
+    if (edge) {
+        float z[F::NPL - 1];
 #pragma unroll
-            for (int q = QLO; q < HI; ++q) bf[(q - QLO) * plane_sz + idx] = dp[q - 1];
+        for (int q = 0; q < F::NPL - 1; ++q) z[q] = 0.0f;
+        for (int t = threadIdx.x; t < IH * IW; t += NT) {
+            const int ri = t / IW, ci = t - ri * IW;
+            if (ri < r0 || ri >= r1 || ci < c0 || ci >= c1) store(ri * IWP + ci, 0.0, z);
         }
+    }
+    const int nc = c1 - c0, npts = (r1 - r0) * nc;
+    // row of a linear index by a float product: (t + 0.5) / nc is below the
+    // row count (< 2^8) and at least 1/(2 nc) > 2^-9 away from an integer,
+    // while the float rounding moves it by less than 2^-14
+    const float rnc = 1.0f / (float)nc;
+    for (int t = threadIdx.x; t < npts; t += NT) {
+        const int rr = (int)(((float)t + 0.5f) * rnc), ri = r0 + rr, ci = c0 + (t - rr * nc);
+        double v0;
+        float dp[F::NPL - 1];
+        planes_at<F, LO == 0>(sh, ti0 - c + ri, tj0 - c + ci, H, v0, dp);
+        store(ri * IWP + ci, v0, dp);
     }
 }
 

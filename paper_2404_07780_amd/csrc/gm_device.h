@@ -90,22 +90,47 @@ __device__ inline double wave_sum(double v)
     return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
 }
 
+// Inclusive prefix sum over the 64 lanes (lane l gets lanes 0..l), in a
+// fixed order: the shift-and-add ladder of wave_sum within each 16-lane row,
+// then the totals of the rows before.
+__device__ inline double wave_scan(double v, int lane)
+{
+    v += dpp_move<0x111>(v);
+    v += dpp_move<0x112>(v);
+    v += dpp_move<0x114>(v);
+    v += dpp_move<0x118>(v);
+    const double t0 = lane_value(v, 15), t1 = lane_value(v, 31), t2 = lane_value(v, 47);
+    const int row = lane >> 4;
+    const double off = row == 0 ? 0.0 : row == 1 ? t0 : row == 2 ? t0 + t1 : (t0 + t1) + t2;
+    return v + off;
+}
+
 // P(a, x) (regularised lower incomplete gamma) and dP/da, one wave: lane l
 // sums the terms k = l, l + 64, l + 128 of the series P = sum_k T_k,
 // T_k = e^-x x^(a+k) / Gamma(a+k+1), dT_k/da = T_k (ln x - psi(a+k+1)).
-// 192 terms cover x <= a + 20 for a <= 20 to double precision; a block of 64
-// terms is skipped once the last term of the previous block is below 1e-17
-// of the sum and the ratio of successive terms, x / (a + k), is below 1/2
-// (the rest of the series is then below twice that last term).
-__device__ inline void gammainc_wave(double a, double x, int lane, bool want_da, double *P, double *dPda)
+// ln Gamma(a+k+1) = ln Gamma(a+1) + sum_{j=1..k} ln(a+j) and
+// psi(a+k+1) = psi(a+1) + sum_{j=1..k} 1/(a+j) are prefix sums over the
+// lanes (lga1 = ln Gamma(a+1), psi1 = psi(a+1)).  192 terms cover
+// x <= a + 20 for a <= 20 to double precision; a block of 64 terms is
+// skipped once the last term of the previous block is below 1e-17 of the
+// sum and the ratio of successive terms, x / (a + k), is below 1/2 (the rest
+// of the series is then below twice that last term).
+__device__ inline void gammainc_wave(double a, double x, double lga1, double psi1, int lane, bool want_da, double *P,
+                                     double *dPda)
 {
-    double lx = log(x), sp = 0.0, sd = 0.0;
+    double lx = log(x), sp = 0.0, sd = 0.0, clg = lga1, cps = psi1;
 #pragma unroll 1
     for (int m = 0; m < 3; ++m) {
-        double k = (double)(lane + 64 * m);
-        double T = exp((a + k) * lx - x - lgamma(a + k + 1.0));
+        const double k = (double)(lane + 64 * m);
+        const double lg = wave_scan(k >= 1.0 ? log(a + k) : 0.0, lane);
+        const double T = exp((a + k) * lx - x - (clg + lg));
         sp += T;
-        if (want_da) sd += T * (lx - digamma(a + k + 1.0));
+        clg += lane_value(lg, 63);
+        if (want_da) {
+            const double ps = wave_scan(k >= 1.0 ? 1.0 / (a + k) : 0.0, lane);
+            sd += T * (lx - (cps + ps));
+            cps += lane_value(ps, 63);
+        }
         if (m < 2 && x < 0.5 * (a + 64.0 * (m + 1)) && lane_value(T, 63) < 1e-17 * wave_sum(sp)) break;
     }
     *P = wave_sum(sp);
@@ -125,11 +150,11 @@ __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
     double in = 1.0 / n;
     double b = a - 1.0 / 3.0 + in * (4.0 / 405.0 + in * (46.0 / 25515.0 + in * (131.0 / 1148175.0)));
     if (!(b > lo && b < hi)) b = 0.5 * a;
-    double lga = lgamma(a);
+    const double lga = lgamma(a), lga1 = lga + log(a);
 #pragma unroll 1
     for (int it = 0; it < 60; ++it) {
         double P;
-        gammainc_wave(a, b, lane, false, &P, nullptr);
+        gammainc_wave(a, b, lga1, 0.0, lane, false, &P, nullptr);
         double f = P - 0.5;
         if (f > 0.0) hi = b; else lo = b;
         double fp = exp((a - 1.0) * log(b) - b - lga);
@@ -142,7 +167,7 @@ __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
         if (st < 1e-14 * b || (newton && pred < 1e-16 * b)) break;
     }
     double P, dPa;
-    gammainc_wave(a, b, lane, true, &P, &dPa);
+    gammainc_wave(a, b, lga1, digamma(a + 1.0), lane, true, &P, &dPa);
     *dbdn = -2.0 * dPa / exp((a - 1.0) * log(b) - b - lga);
     return b;
 }

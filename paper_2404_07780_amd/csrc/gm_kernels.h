@@ -311,17 +311,57 @@ __device__ inline void load_seg(const T *p, T *seg)
     }
 }
 
+// Taps v0 .. v1-1 of one PSF row against the segment elements e0 .. (e0 a
+// multiple of the 16-byte vector width): acc[t] += sum_v p[v] seg[KT-1-v+t].
+template <int KT, int V0, int V1, int E0, typename T>
+__device__ inline void row_part(const T *rp, const cfloat *pr, T &a0, T &a1, T &a2, T &a3)
+{
+    constexpr int PER = 16 / sizeof(T);
+    constexpr int N = ((KT + 2 - V0) - E0 + 1 + PER - 1) / PER * PER;
+    T seg[N];
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const V *vp = reinterpret_cast<const V *>(rp + E0);
+#pragma unroll
+    for (int q = 0; q < N / PER; ++q) {
+        V t = vp[q];
+        if constexpr (sizeof(T) == 4) {
+            seg[4 * q] = t.x; seg[4 * q + 1] = t.y; seg[4 * q + 2] = t.z; seg[4 * q + 3] = t.w;
+        } else {
+            seg[2 * q] = t.x; seg[2 * q + 1] = t.y;
+        }
+    }
+#pragma unroll
+    for (int v = V0; v < V1; ++v) {
+        const T pv = (T)pr[v];
+        a0 = fma(pv, seg[KT - 1 - v - E0], a0);
+        a1 = fma(pv, seg[KT - v - E0], a1);
+        a2 = fma(pv, seg[KT + 1 - v - E0], a2);
+        a3 = fma(pv, seg[KT + 2 - v - E0], a3);
+    }
+}
+
 // Convolve one plane (elements of type T, row pitch IWP) for a 1 x 4 output
-// strip with a compile-time PSF side.  FP32 planes load the segment of the
-// next PSF row while the current one is used; the FP64 plane, whose segment
-// is twice as large, loads one row at a time.
+// strip with a compile-time PSF side.  Up to side 15, FP32 planes load the
+// segment of the next PSF row while the current one is used and the FP64
+// plane, whose segment is twice as large, loads one row at a time.  Wider
+// PSFs take each row in two halves of taps, each with only the part of the
+// segment it reads, so that the kernel fits two workgroups' registers.
 template <int KT, typename T>
 __device__ inline void conv_plane(const T *base, int r, int IWP, const cfloat *psf, T (&out)[4])
 {
     constexpr int PER = 16 / sizeof(T);
     constexpr int SEG = ((KT + 3 + PER - 1) / PER) * PER;
     T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (KT > 15) {
+        // taps v < VS read elements from ES on, taps v >= VS elements from 0
+        constexpr int ES = 4 * ((KT - 1) / 8), VS = KT - ES;
+#pragma unroll 1
+        for (int u = 0; u < KT; ++u) {
+            const T *rp = base + (r + KT - 1 - u) * IWP;
+            row_part<KT, 0, VS, ES>(rp, psf + u * KT, a0, a1, a2, a3);
+            row_part<KT, VS, KT, 0>(rp, psf + u * KT, a0, a1, a2, a3);
+        }
+    } else if constexpr (sizeof(T) == 4) {
         T sa[SEG], sb[SEG];
         load_seg<KT>(base + (r + KT - 1) * IWP, sa);
 #pragma unroll 1
@@ -923,18 +963,18 @@ __device__ void load_u(LMShared<F> &s, const ModelArgs &ma, const double *params
     }
 }
 
-// Workgroups per CU that the fit kernel's register allocation targets.  Two (at most 256 VGPRs per lane) let one workgroup's profile
-// evaluation, prologue and LM step overlap the other's convolution; the
-// one-component families fit them with the compile-time PSF side 15 and no
-// spills inside loops (measured 1.38x faster Sersic fits at 64 x 64).  With
-// side 25 the unrolled row segments would spill inside the convolution, and
-// the two-component models need more registers than that for their
-// accumulators, so those keep one (as does the error kernel, which would
+// Workgroups per CU that the fit kernel's register allocation targets.  Two
+// (at most 256 VGPRs per lane) let one workgroup's profile evaluation,
+// prologue and LM step overlap the other's convolution, where the plane
+// buffers of two fit in LDS.  The one-component families fit them without
+// spills inside loops (measured 1.38x faster Sersic fits at 64 x 64, PSF
+// side 15); the two-component models need more registers than that for
+// their accumulators and keep one (as does the error kernel, which would
 // spill inside its loops).
 template <class F, int KT>
 __host__ __device__ constexpr int min_wg()
 {
-    return (F::NCOMP == 1 && KT == 15) ? 2 : 1;
+    return F::NCOMP == 1 ? 2 : 1;
 }
 
 template <class F, int KT, int NG>

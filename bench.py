@@ -7,9 +7,10 @@ timed region the proposal network is trained on the GPU by the library's own
 kernels on 1,048,576 galaxies made by the forward model (reported, untimed).
 One timed step = the whole hot path over the held-out batch resident in HBM:
 gm_fit_learned (moments, features, network, decoding, LM from the proposals,
-fallback LM from the moment start) and gm_param_errors.  The same galaxies
-are then fitted by plain LM from the moment start (gm_default_guess +
-gm_fit_batch + gm_param_errors) for the speedup.
+fallback LM from the moment start) with the covariance errors at the fit,
+replayed as a captured plan (HIP graph).  The same galaxies are then fitted
+by plain LM from the moment start (gm_default_guess + gm_fit_batch with
+errors, also a plan) for the speedup.  --eager times the calls themselves.
 
 Other workloads (plain LM only): "uneven" (8,192 galaxies, cutouts 48-256 px,
 per-galaxy 25x25 Moffat PSFs, Poisson + read noise), "sersic64", "bulgedisk".
@@ -299,23 +300,24 @@ def main():
     status = torch.empty(n, dtype=torch.int32, device=dev)
     fallback = torch.empty(n, dtype=torch.int32, device=dev)
 
+    err = torch.empty(n, p, dtype=torch.float64, device=dev)
+
+    # a step: start vectors, LM, covariance errors at the fit (computed by the
+    # fit kernel from its last normal matrix)
     def plain_step(ev):
         if ev:
             ev[0].record(stream)
         guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
         if ev:
             ev[1].record(stream)
-        G.gm_fit_batch(gm, db, guess, ctx=ctx, out=(params, chi2, niter, status))
+        G.gm_fit_batch(gm, db, guess, ctx=ctx, out=(params, chi2, niter, status), err_out=err)
         if ev:
             ev[2].record(stream)
-        G.gm_param_errors(gm, db, params, ctx=ctx)
-        if ev:
             ev[3].record(stream)
 
     def learned_step(ev):
         G.gm_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter, ctx=ctx,
-                         out=(params, chi2, niter, status, fallback), events=ev)
-        G.gm_param_errors(gm, db, params, ctx=ctx)
+                         out=(params, chi2, niter, status, fallback), events=ev, err_out=err)
 
     names = ("learned", "plain") if learned else ("plain",)
     plans = {}
@@ -354,10 +356,10 @@ def main():
             extra = dict(fallback_invalid=int((fb == 1).sum()), fallback_unconverged=int((fb == 2).sum()))
             kernel = "lm_fit_kernel (proposal launch + fallback launch)"
         else:
-            # events: before the guess, before and after the LM, after the errors
+            # events: before the guess, before and after the LM (errors inside), the end
             lm_ms = [r[1] for r in seg]
             evals = 1.0 + nit
-            extra = dict(guess_ms=float(np.mean([r[0] for r in seg])), errors_ms=float(np.mean([r[2] for r in seg])))
+            extra = dict(guess_ms=float(np.mean([r[0] for r in seg])))
             kernel = "lm_fit_kernel"
         conv = st == G.ST_CONVERGED
         if name == "learned":

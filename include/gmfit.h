@@ -100,6 +100,12 @@ typedef struct {
                                  skipped and their outputs left untouched */
     int32_t proposal_max_iter;  /* gm_fit_learned: trials of the LM from the learned start
                                    before the fallback (0 = max_iter) */
+    double *err_out;          /* DEVICE [n_gal][p] or NULL: covariance errors at the fit, the
+                                 values gm_param_errors gives at the fitted (canonical)
+                                 parameters, from the normal matrix of the last accepted
+                                 evaluation (no extra evaluation).  Where a component with
+                                 a fixed scale is put in canonical form, they are the
+                                 errors of the fitted model in the canonical variables. */
 } gm_fit_opts;
 
 typedef struct gm_ctx gm_ctx;
@@ -319,15 +325,16 @@ int gm_synth_noise(gm_ctx *ctx, int32_t n_gal, const int32_t *h, const int32_t *
 typedef struct gm_plan gm_plan;
 
 /* params_out <- start (device [n_gal][p]; NULL: the moment-based guess of
- * gm_default_guess), then gm_fit_batch, then (err_out not NULL)
- * gm_param_errors at the fit.  timing != 0: the plan records four events of
+ * gm_default_guess), then gm_fit_batch with the covariance errors at the fit
+ * in err_out (nullable; gm_fit_opts.err_out is ignored).  timing != 0: the plan records four events of
  * its own as graph nodes -- before the start, before and after the LM
  * launch, at the end -- read with gm_plan_elapsed. */
 int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
                 const double *start, double *params_out, double *chi2_out, int32_t *niter_out,
                 int32_t *status_out, double *err_out, int32_t timing, gm_plan **out);
 
-/* gm_fit_learned, then (err_out not NULL) gm_param_errors at the fit.
+/* gm_fit_learned with the covariance errors at the fit in err_out (nullable;
+ * gm_fit_opts.err_out is ignored).
  * timing != 0: four events as those of gm_fit_learned (before and after the
  * LM launch from the proposals, before and after the fallback LM launch),
  * read with gm_plan_elapsed. */

@@ -714,10 +714,11 @@ int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const
             rc = v->guess(pc, mt.ci, params_out, nullptr, st);
         }
     }
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
+    o.err_out = err_out;
     if (!rc) rc = mark_event(pc, events, 1, st);
-    if (!rc) rc = v->fit(pc, mt.ci, opts, params_out, chi2_out, niter_out, status_out, st);
+    if (!rc) rc = v->fit(pc, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
     if (!rc) rc = mark_event(pc, events, 2, st);
-    if (!rc && err_out) rc = v->errors(pc, mt.ci, params_out, err_out, nullptr, st);
     if (!rc) rc = mark_event(pc, events, 3, st);
     return plan_end(p, rc, out);
 }

@@ -662,6 +662,102 @@ __device__ void canonical_nat(const double *u, const int *freev, double *nat)
     }
 }
 
+// Covariance errors of a fit, sqrt(diag (J^T W J)^-1) (Sec. 5.2), from the
+// normal matrix of the last accepted evaluation (J^T W J at u), in natural
+// units of the canonical form written by canonical_nat.  Where that form
+// flips a component (q -> 1/q, each scale s -> s q, theta -> theta + pi/2),
+// the model image is unchanged, so the Jacobian in the canonical variables is
+// J Phi^-1 with Phi the Jacobian of the flip in the LM variables (ln s' =
+// ln s + ln q, q' = 1/q) and the covariance becomes Phi (J^T W J)^-1 Phi^T:
+// the errors gm_param_errors computes at the canonical parameters, without
+// another evaluation.  Fixed slots have identity rows (as in the error
+// kernel); a matrix that is not positive definite gives NaN.  One thread,
+// every array in LDS and every loop rolled, so that it adds no registers to
+// the fit's loops; scratch: 3 P^2 + 2 P doubles.  A is overwritten.
+template <class F>
+__device__ void fit_errors(double *A, double *g, const double *u, const int *freev, const ModelArgs &ma, double *err,
+                           double *scratch)
+{
+    constexpr int P = F::P;
+    double *L = scratch, *inv = L + P * P, *phi = inv + P * P, *nat = phi + P * P, *y = nat + P;
+    project_fixed<P>(freev, A, g);
+    // Cholesky A = L L^T
+    bool ok = true;
+#pragma unroll 1
+    for (int j = 0; j < P && ok; ++j) {
+        double d = A[j * P + j];
+#pragma unroll 1
+        for (int k = 0; k < j; ++k) d -= L[j * P + k] * L[j * P + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            ok = false;
+            break;
+        }
+        const double lj = sqrt(d);
+        L[j * P + j] = lj;
+#pragma unroll 1
+        for (int i = j + 1; i < P; ++i) {
+            double t = A[i * P + j];
+#pragma unroll 1
+            for (int k = 0; k < j; ++k) t -= L[i * P + k] * L[j * P + k];
+            L[i * P + j] = t / lj;
+        }
+    }
+    if (!ok) {
+#pragma unroll 1
+        for (int k = 0; k < P; ++k)
+            if (ma.col[k] >= 0) err[ma.col[k]] = NAN;
+        return;
+    }
+    // inverse, column by column: L y = e_j, then L^T x = y
+#pragma unroll 1
+    for (int j = 0; j < P; ++j) {
+#pragma unroll 1
+        for (int i = 0; i < P; ++i) {
+            double t = (i == j) ? 1.0 : 0.0;
+#pragma unroll 1
+            for (int k = 0; k < i; ++k) t -= L[i * P + k] * y[k];
+            y[i] = t / L[i * P + i];
+        }
+#pragma unroll 1
+        for (int i = P - 1; i >= 0; --i) {
+            double t = y[i];
+#pragma unroll 1
+            for (int k = i + 1; k < P; ++k) t -= L[k * P + i] * inv[k * P + j];
+            inv[i * P + j] = t / L[i * P + i];
+        }
+    }
+    // Phi: identity, with the flip's rows for components canonical_nat flips
+#pragma unroll 1
+    for (int k = 0; k < P * P; ++k) phi[k] = (k % (P + 1) == 0) ? 1.0 : 0.0;
+#pragma unroll 1
+    for (int c = 0; c < F::NCAN; ++c) {
+        int iq, ith, is0, is1;
+        F::canon(c, iq, ith, is0, is1);
+        const double q = u[iq];
+        if (freev[iq] && freev[ith] && q > 1.0) {
+            phi[iq * P + iq] = -1.0 / (q * q);
+            if (is0 >= 0) phi[is0 * P + iq] = 1.0 / q;
+            if (is1 >= 0) phi[is1 * P + iq] = 1.0 / q;
+        }
+    }
+    canonical_nat<F>(u, freev, nat);
+    // diag(Phi inv Phi^T)
+#pragma unroll 1
+    for (int a = 0; a < P; ++a) {
+        if (ma.col[a] < 0) continue;
+        double v = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < P; ++k) {
+            if (phi[a * P + k] == 0.0) continue;
+            double t = 0.0;
+#pragma unroll 1
+            for (int l = 0; l < P; ++l) t += inv[k * P + l] * phi[a * P + l];
+            v += phi[a * P + k] * t;
+        }
+        err[ma.col[a]] = sqrt(v) * fabs(dnat_du(F::kind(a), nat[a]));
+    }
+}
+
 // ---------------------------------------------------------------- LM kernel
 template <class F>
 struct LMShared {
@@ -680,6 +776,7 @@ struct FitArgs {
     int *queue;
     double *params, *chi2;
     int *niter, *status;
+    double *err;              // nullable: covariance errors at the fit [n_gal][p]
     int max_iter;
     double lambda0, tol;
 };
@@ -1029,6 +1126,9 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             fa.chi2[g] = s.chi2;
             fa.niter[g] = s.t;
             fa.status[g] = s.status;
+            if (fa.err)
+                fit_errors<F>(s.A, s.g, s.u, s.freev, ma, fa.err + (int64_t)g * ma.p,
+                              reinterpret_cast<double *>(planes));
         }
         __syncthreads();
     }

@@ -234,6 +234,7 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     fa.chi2 = chi2;
     fa.niter = niter;
     fa.status = status;
+    fa.err = o ? o->err_out : nullptr;
     fa.max_iter = o ? o->max_iter : 100;
     fa.lambda0 = o ? o->lambda0 : 1e-3;
     fa.tol = o ? o->step_tol : 1e-4;

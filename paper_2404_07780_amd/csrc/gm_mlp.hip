@@ -791,7 +791,7 @@ int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *
     rc = decode_launch(ctx, mt, out, mlp->out_dim, mom8, params_out, valid, st);
     if (rc) return rc;
     // LM from the valid proposals
-    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0};
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
     const int full_iter = o.max_iter;
     if (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) o.max_iter = o.proposal_max_iter;
     o.active = valid;
@@ -975,10 +975,11 @@ int gm_plan_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batc
     // the workspace is sized before the capture, which then allocates nothing
     if (!rc) rc = ensure_ws(pc, learned_ws_bytes(mlp, batch->n_gal, model->p));
     if (!rc) rc = plan_begin(p);
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
+    o.err_out = err_out;
     if (!rc)
-        rc = learned_seq(pc, mt, var, mlp, opts, params_out, chi2_out, niter_out, status_out, fallback_out, events,
+        rc = learned_seq(pc, mt, var, mlp, &o, params_out, chi2_out, niter_out, status_out, fallback_out, events,
                          p->stream);
-    if (!rc && err_out) rc = var->errors(pc, mt.ci, params_out, err_out, nullptr, p->stream);
     return plan_end(p, rc, out);
 }
 

@@ -55,7 +55,7 @@ class gm_batch(C.Structure):
 
 class gm_fit_opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double),
-                ("active", C.c_void_p), ("proposal_max_iter", C.c_int32)]
+                ("active", C.c_void_p), ("proposal_max_iter", C.c_int32), ("err_out", C.c_void_p)]
 
 
 class gm_schedule(C.Structure):
@@ -262,6 +262,15 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _err_ptr(err_out: Optional[torch.Tensor], batch: "Batch", model: "Model"):
+    if err_out is None:
+        return None
+    if (err_out.dtype != torch.float64 or err_out.device != batch.device or not err_out.is_contiguous()
+            or err_out.numel() != batch.n * model.p):
+        raise ValueError("err_out: contiguous float64 device tensor of n_gal * p values")
+    return err_out.data_ptr()
+
+
 def _params_dev(params, batch: Batch, p: int) -> torch.Tensor:
     t = params if isinstance(params, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(params, np.float64))
     t = t.to(device=batch.device, dtype=torch.float64).contiguous()
@@ -334,11 +343,13 @@ def gm_default_guess(model: Model, batch: Batch, ctx: Optional[Context] = None):
 
 
 def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambda0: float = 1e-3,
-                 step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None, active=None):
+                 step_tol: float = 1e-4, ctx: Optional[Context] = None, out=None, active=None,
+                 err_out: Optional[torch.Tensor] = None):
     """Returns (params, chi2, niter, status) as device tensors.  `out` may pass
     preallocated (params, chi2, niter, status); params is then overwritten with
     params0 first unless params0 is None.  `active` (device int32 [n]) skips
-    the galaxies where it is 0."""
+    the galaxies where it is 0.  `err_out` (device float64 [n, p]) receives
+    the covariance errors at the fit."""
     ctx = ctx or context(batch.device.index)
     if out is None:
         params = _params_dev(params0, batch, model.p).clone()
@@ -349,7 +360,8 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
         params, chi2, niter, status = out
         if params0 is not None:
             params.copy_(_params_dev(params0, batch, model.p))
-    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr(), 0)
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr(), 0,
+                    _err_ptr(err_out, batch, model))
     m, b = model.c(), batch.c()
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
@@ -502,11 +514,12 @@ def gm_proposal_decode(model: Model, batch: Batch, out: torch.Tensor, moments: t
 
 def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, lambda0: float = 1e-3,
                    step_tol: float = 1e-4, proposal_max_iter: int = 50, ctx: Optional[Context] = None, out=None,
-                   events=None):
+                   events=None, err_out: Optional[torch.Tensor] = None):
     """(params, chi2, niter, status, fallback) as device tensors.  The LM from the
     learned start gets proposal_max_iter trials (0: max_iter) before the
     fallback.  events: four recorded torch.cuda.Event objects that the library
-    re-records around its two LM launches."""
+    re-records around its two LM launches.  err_out (device float64 [n, p])
+    receives the covariance errors at the fit."""
     ctx = _ctx_for(batch.device, ctx)
     if out is None:
         params = torch.zeros(batch.n, model.p, dtype=torch.float64, device=batch.device)
@@ -516,7 +529,8 @@ def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, la
         fallback = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
     else:
         params, chi2, niter, status, fallback = out
-    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, int(proposal_max_iter))
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, int(proposal_max_iter),
+                    _err_ptr(err_out, batch, model))
     m, b, ml = model.c(), batch.c(), mlp.c()
     ev = _events4(events)
     _check("gm_fit_learned", lib().gm_fit_learned(ctx.handle, C.byref(m), C.byref(b), C.byref(ml), C.byref(o),

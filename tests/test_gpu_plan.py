@@ -1,5 +1,5 @@
 """Captured plans (gm_plan_fit, gm_plan_fit_learned): every graph replay gives
-the eager calls' results bit for bit -- the same kernels run on the same
+the eager calls' results (fit with its covariance errors) bit for bit -- the same kernels run on the same
 inputs -- including replays separated by other eager work on the parent
 context (which grows and overwrites its own workspace) and by changes of the
 plan's inputs.  The eager calls themselves are held to the oracle by the
@@ -57,8 +57,8 @@ def test_plan_fit_replays_equal_eager(cfg, n, with_start):
 
     def eager():
         p0 = start.clone() if with_start else G.gm_default_guess(gm, db, ctx=ctx)[0]
-        p, c, it, st = G.gm_fit_batch(gm, db, p0, ctx=ctx)
-        err = G.gm_param_errors(gm, db, p, ctx=ctx)
+        err = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
+        p, c, it, st = G.gm_fit_batch(gm, db, p0, ctx=ctx, err_out=err)
         return _np(p, c, it, st, err)
 
     ref = eager()
@@ -89,8 +89,8 @@ def test_plan_fit_learned_replays_equal_eager():
     # the budget of 10 trials sends the rest to the fallback
     mlp = G.MLP(np.zeros(M.param_count(), np.float32), train=False)
     plan = G.gm_plan_fit_learned(gm, db, mlp, proposal_max_iter=10, errors=True, ctx=ctx)
-    p, c, it, st, fb = G.gm_fit_learned(gm, db, mlp, proposal_max_iter=10, ctx=ctx)
-    err = G.gm_param_errors(gm, db, p, ctx=ctx)
+    err = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
+    p, c, it, st, fb = G.gm_fit_learned(gm, db, mlp, proposal_max_iter=10, ctx=ctx, err_out=err)
     ref = _np(p, c, it, st, fb, err)
     print(f"learned plan: fallback codes {np.bincount(ref[4], minlength=3).tolist()}", flush=True)
     assert (ref[4] == 0).any() and (ref[4] == 2).any()

@@ -120,7 +120,7 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
     return 2.0 * hw * k2 * npl, 2.0 * hw * (p * (p + 1) / 2 + p + 1)
 
 
-def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 50):
+def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20):
     """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
     noised on the host), all host cores, LM from its own moment start; the GPU
     fits of the same data (plain, and learned when a network is given) are
@@ -240,7 +240,7 @@ def main():
     ap.add_argument("--train-n", type=int, default=1 << 20, help="training galaxies (learned workload)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=4096)
-    ap.add_argument("--proposal-max-iter", type=int, default=50,
+    ap.add_argument("--proposal-max-iter", type=int, default=20,
                     help="LM trials from the learned start before the moment-start fallback")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="oracle sample size (0 = skip; default: learned 2048, sersic64 64, others 160)")

@@ -513,7 +513,7 @@ def gm_proposal_decode(model: Model, batch: Batch, out: torch.Tensor, moments: t
 
 
 def gm_fit_learned(model: Model, batch: Batch, mlp: MLP, max_iter: int = 100, lambda0: float = 1e-3,
-                   step_tol: float = 1e-4, proposal_max_iter: int = 50, ctx: Optional[Context] = None, out=None,
+                   step_tol: float = 1e-4, proposal_max_iter: int = 20, ctx: Optional[Context] = None, out=None,
                    events=None, err_out: Optional[torch.Tensor] = None):
     """(params, chi2, niter, status, fallback) as device tensors.  The LM from the
     learned start gets proposal_max_iter trials (0: max_iter) before the
@@ -616,7 +616,7 @@ def gm_plan_fit(model: Model, batch: Batch, start=None, errors: bool = True, max
 
 
 def gm_plan_fit_learned(model: Model, batch: Batch, mlp: "MLP", errors: bool = True, max_iter: int = 100,
-                        lambda0: float = 1e-3, step_tol: float = 1e-4, proposal_max_iter: int = 50,
+                        lambda0: float = 1e-3, step_tol: float = 1e-4, proposal_max_iter: int = 20,
                         timing: bool = False, ctx: Optional[Context] = None) -> Plan:
     """Capture gm_fit_learned -> (errors) on this batch; the network's weights
     are read at each launch."""

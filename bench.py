@@ -47,10 +47,10 @@ METRIC = "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs p
 # (scaled by the counts of a 1 GiB copy: FETCH x 2.0, WRITE x 1.0), keyed by
 # workload and the hash of the library sources they were taken with.
 TRAFFIC = {
-    # profiles/lm_fit_learned65536.md: proposal + fallback LM launches of one learned step
-    "learned:65536:2:1ac598db38566684": 2.387838e+09,
+    # profiles/lm_fit_learned65536.md: the two LM launches of one learned step
+    "learned:65536:2:6acea46f26ff9d31": 3.568239e+09,
     # profiles/lm_fit_uneven8192.md: one LM launch
-    "uneven:8192:0:1ac598db38566684": 1.321998e+10,
+    "uneven:8192:0:6acea46f26ff9d31": 1.305287e+10,
 }
 
 
@@ -244,8 +244,9 @@ def main():
                     help="LM trials from the learned start before the moment-start fallback")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="oracle sample size (0 = skip; default: learned 2048, sersic64 64, others 160)")
-    ap.add_argument("--tune-sample", type=int, default=2048,
-                    help="galaxies timed per candidate schedule before the timed region (0 = library default)")
+    ap.add_argument("--tune-sample", type=int, default=-1,
+                    help="galaxies fitted to completion per candidate schedule before the timed region "
+                         "(-1 = the whole batch, 0 = library default schedule)")
     ap.add_argument("--eager", action="store_true",
                     help="time the eager calls instead of replays of the captured plans")
     ap.add_argument("--calib", action="store_true",
@@ -281,7 +282,8 @@ def main():
     from paper_2404_07780_amd import tune
 
     t0 = time.perf_counter()
-    sched = tune.apply(gm, db, sample=args.tune_sample) if args.tune_sample > 0 else None
+    sched = (tune.apply(gm, db, sample=n if args.tune_sample < 0 else args.tune_sample, trials=0)
+             if args.tune_sample != 0 else None)
     if sched:
         log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']} "
             f"(tuned in {time.perf_counter() - t0:.1f} s: {[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 1)) for t in sched['trials']]})")
@@ -402,7 +404,7 @@ def main():
                    **({"proposal_max_iter": args.proposal_max_iter} if learned else {})},
         "roofline": {"bound": "alu", "achieved": head["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": head["achieved"] / PEAK_FP32_TFLOPS, "traffic": TRAFFIC.get(key),
-                     "traffic_unit": "HBM bytes per launch", "kernel": head["kernel"], "kernel_ms": head["lm_ms"],
+                     "traffic_unit": "HBM bytes per step (its LM launches)", "kernel": head["kernel"], "kernel_ms": head["lm_ms"],
                      "flops_per_step": head["flops"]},
         "lm": {k: v for k, v in head.items() if k not in ("value", "ms_per_step", "achieved", "flops", "kernel")},
         "schedule": (None if not sched else

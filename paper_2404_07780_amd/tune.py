@@ -4,7 +4,13 @@ For a model and a batch, every plane-group count compiled for the model's
 family (gm_schedule_options) is tried with the persistent grid at full
 residency and at one workgroup per CU: the LM fit from the moment start runs
 on a sample of the batch under each schedule (gm_set_schedule) and the
-fastest is kept.  Results are cached in a JSON file keyed by
+fastest is kept.  By default each galaxy of a sample gets a fixed number of
+trials, so that every schedule does the same work and the time measures the
+throughput per evaluation rather than the few slowest fits of the sample;
+with trials=0 the fits run to completion, which also measures how a schedule
+copes with the slowest fits (it matters for batches of very uneven cutouts,
+where the largest fits that need the most trials finish last and run at half
+speed when two workgroups share a CU).  Results are cached in a JSON file keyed by
 (device architecture, family, PSF side, parameter count, cutout-size bucket),
 so later runs apply a known schedule without timing.
 """
@@ -50,35 +56,37 @@ def subset(batch: G.Batch, n: int) -> G.Batch:
                    batch.sigma, batch.psf, omega=batch.omega, device=batch.device)
 
 
-def _time_fit(model, sb, start, ctx, reps: int) -> float:
-    G.gm_fit_batch(model, sb, start, ctx=ctx)            # warm-up (kernel load, workspace growth)
+def _time_fit(model, sb, start, ctx, reps: int, trials: int) -> float:
+    mi = trials if trials > 0 else 100
+    G.gm_fit_batch(model, sb, start, ctx=ctx, max_iter=mi)      # warm-up (kernel load, workspace growth)
     best = float("inf")
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        G.gm_fit_batch(model, sb, start, ctx=ctx)
+        G.gm_fit_batch(model, sb, start, ctx=ctx, max_iter=mi)
         e1.record()
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return best
 
 
-def tune(model: G.Model, batch: G.Batch, sample: int = 2048, reps: int = 2,
+def tune(model: G.Model, batch: G.Batch, sample: int = 4096, reps: int = 3, trials: int = 4,
          ctx: Optional[G.Context] = None) -> Dict:
-    """Time every schedule on the first `sample` galaxies, apply the fastest and
-    return {"plane_groups", "wg_per_cu", "ms", "trials"}."""
+    """Time every schedule on the first `sample` galaxies with `trials` LM trials
+    each (0: complete fits), apply the fastest and return {"plane_groups",
+    "wg_per_cu", "ms", "trials" (every schedule's time)}."""
     ctx = ctx or G.context(batch.device.index)
     k = batch_psf_side(batch)
     sb = subset(batch, sample)
     start, _ = G.gm_default_guess(model, sb, ctx=ctx)
-    trials = []
+    results = []
     for ng in G.gm_schedule_options(model, k if k else int(batch.psf_k.max())):
         for wpc in (0, 1):
             G.gm_set_schedule(model, k, ng, wpc, ctx=ctx)
-            trials.append(dict(plane_groups=ng, wg_per_cu=wpc, ms=_time_fit(model, sb, start, ctx, reps)))
-    best = min(trials, key=lambda t: t["ms"])
+            results.append(dict(plane_groups=ng, wg_per_cu=wpc, ms=_time_fit(model, sb, start, ctx, reps, trials)))
+    best = min(results, key=lambda t: t["ms"])
     G.gm_set_schedule(model, k, best["plane_groups"], best["wg_per_cu"], ctx=ctx)
-    return dict(best, trials=trials, sample=sb.n)
+    return dict(best, trials=results, sample=sb.n, trials_per_galaxy=trials)
 
 
 def load(path: str) -> Dict:
@@ -95,7 +103,7 @@ def save(path: str, cache: Dict) -> None:
     os.replace(tmp, path)
 
 
-def apply(model: G.Model, batch: G.Batch, cache_path: Optional[str] = None, sample: int = 2048,
+def apply(model: G.Model, batch: G.Batch, cache_path: Optional[str] = None, sample: int = 4096, trials: int = 4,
           ctx: Optional[G.Context] = None) -> Dict:
     """Apply the cached schedule for this model and batch, tuning (and caching,
     when a path is given) if there is none."""
@@ -106,7 +114,7 @@ def apply(model: G.Model, batch: G.Batch, cache_path: Optional[str] = None, samp
         e = cache[key]
         G.gm_set_schedule(model, batch_psf_side(batch), e["plane_groups"], e["wg_per_cu"], ctx=ctx)
         return dict(e, key=key, cached=True)
-    res = tune(model, batch, sample=sample, ctx=ctx)
+    res = tune(model, batch, sample=sample, trials=trials, ctx=ctx)
     if cache_path:
         cache[key] = {k: res[k] for k in ("plane_groups", "wg_per_cu", "ms")}
         save(cache_path, cache)

@@ -337,12 +337,8 @@ def main():
     for name in names:
         if args.eager:
             wall, evs = timed(learned_step if name == "learned" else plain_step, args.steps, args.warmup, name)
-            if name == "learned":
-                seg = [[evs[i][0].elapsed_time(evs[i][1]), 0.0, evs[i][2].elapsed_time(evs[i][3])]
-                       for i in range(args.steps)]
-            else:
-                seg = [[evs[i][0].elapsed_time(evs[i][1]), evs[i][1].elapsed_time(evs[i][2]),
-                        evs[i][2].elapsed_time(evs[i][3])] for i in range(args.steps)]
+            seg = [[evs[i][0].elapsed_time(evs[i][1]), evs[i][1].elapsed_time(evs[i][2]),
+                    evs[i][2].elapsed_time(evs[i][3])] for i in range(args.steps)]
             out_t = (params, niter, status, fallback)
         else:
             plan = plans[name]
@@ -352,11 +348,12 @@ def main():
         st = out_t[2].cpu().numpy()
         if name == "learned":
             fb = out_t[3].cpu().numpy()
-            # events: before/after the LM from the proposals, before/after the fallback LM
-            lm_ms = [r[0] + r[2] for r in seg]
+            # events: before the moment guess, before and after the LM launch (fits from the
+            # proposals and refits from the moment start), the end
+            lm_ms = [r[1] for r in seg]
             evals = 1.0 + nit + (fb == 2)
             extra = dict(fallback_invalid=int((fb == 1).sum()), fallback_unconverged=int((fb == 2).sum()))
-            kernel = "lm_fit_kernel (proposal launch + fallback launch)"
+            kernel = "lm_fit_kernel (fits from the proposals, refits from the moment start in the same launch)"
         else:
             # events: before the guess, before and after the LM (errors inside), the end
             lm_ms = [r[1] for r in seg]

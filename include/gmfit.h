@@ -281,13 +281,13 @@ int gm_proposal_decode(gm_ctx *ctx, const gm_model *model, const gm_batch *batch
 /* LM from the network's proposal with the moment-based guess as fallback:
  * galaxies whose proposal is invalid, or whose LM from it does not end
  * GM_ST_CONVERGED within opts->proposal_max_iter trials, are refitted from
- * gm_default_guess (with opts->max_iter trials); their reported result
- * is the refit and niter_out counts the trials of both fits.  fallback_out
- * (device, nullable) [n_gal]: 0 = fitted from the proposal, 1 = proposal
- * invalid, 2 = LM from the proposal did not converge (refitted).
- * events (nullable): four hipEvent_t recorded on the stream before and after
- * the LM launch from the proposals and before and after the fallback LM
- * launch (profiling).  opts->active is ignored.  Same model restriction as
+ * gm_default_guess (with opts->max_iter trials) by the same workgroup of the
+ * same launch; their reported result is the refit and niter_out counts the
+ * trials of both fits.  fallback_out (device, nullable) [n_gal]: 0 = fitted
+ * from the proposal, 1 = proposal invalid, 2 = LM from the proposal did not
+ * converge (refitted).  events (nullable): four hipEvent_t recorded on the
+ * stream before the moment guess, before and after the LM launch, and at the
+ * end (profiling).  opts->active is ignored.  Same model restriction as
  * gm_proposal_decode. */
 int gm_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
                    const gm_fit_opts *opts, double *params_out, double *chi2_out,
@@ -326,18 +326,16 @@ typedef struct gm_plan gm_plan;
 
 /* params_out <- start (device [n_gal][p]; NULL: the moment-based guess of
  * gm_default_guess), then gm_fit_batch with the covariance errors at the fit
- * in err_out (nullable; gm_fit_opts.err_out is ignored).  timing != 0: the plan records four events of
- * its own as graph nodes -- before the start, before and after the LM
- * launch, at the end -- read with gm_plan_elapsed. */
+ * in err_out (nullable; gm_fit_opts.err_out is ignored).  timing != 0: the
+ * plan records four events of its own as graph nodes -- before the start,
+ * before and after the LM launch, at the end -- read with gm_plan_elapsed. */
 int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
                 const double *start, double *params_out, double *chi2_out, int32_t *niter_out,
                 int32_t *status_out, double *err_out, int32_t timing, gm_plan **out);
 
 /* gm_fit_learned with the covariance errors at the fit in err_out (nullable;
- * gm_fit_opts.err_out is ignored).
- * timing != 0: four events as those of gm_fit_learned (before and after the
- * LM launch from the proposals, before and after the fallback LM launch),
- * read with gm_plan_elapsed. */
+ * gm_fit_opts.err_out is ignored).  timing != 0: four events as those of
+ * gm_fit_learned, read with gm_plan_elapsed. */
 int gm_plan_fit_learned(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_mlp *mlp,
                         const gm_fit_opts *opts, double *params_out, double *chi2_out,
                         int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,

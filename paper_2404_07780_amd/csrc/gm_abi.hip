@@ -666,7 +666,7 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     Scoped sd(ctx->device);
     const Variant *v;
     if ((rc = pick_variant(ctx, mt, &v))) return rc;
-    return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, (hipStream_t)stream);
+    return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, nullptr, (hipStream_t)stream);
 }
 
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params,
@@ -717,7 +717,7 @@ int gm_plan_fit(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const
     gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
     o.err_out = err_out;
     if (!rc) rc = mark_event(pc, events, 1, st);
-    if (!rc) rc = v->fit(pc, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    if (!rc) rc = v->fit(pc, mt.ci, &o, params_out, chi2_out, niter_out, status_out, nullptr, st);
     if (!rc) rc = mark_event(pc, events, 2, st);
     if (!rc) rc = mark_event(pc, events, 3, st);
     return plan_end(p, rc, out);

@@ -765,7 +765,7 @@ struct LMShared {
     double Dg[F::P], sig[F::P], delta[F::P];
     double chi2, chi2t, lambda;
     int freev[F::P];
-    int t, status, fresh, apd, action;
+    int t, status, fresh, apd, action, max_iter;
     int gal;
 };
 
@@ -779,6 +779,16 @@ struct FitArgs {
     double *err;              // nullable: covariance errors at the fit [n_gal][p]
     int max_iter;
     double lambda0, tol;
+    // Refit (nullable refit_start): a galaxy whose fit from params ends other
+    // than CONVERGED within first_max_iter trials, or whose valid[g] is 0 (its
+    // params are not a usable start), is fitted again, at once and by the same
+    // workgroup, from refit_start[g] with max_iter trials; niter counts the
+    // trials of both fits and refit_code[g] (nullable) is 0 (first fit), 1
+    // (unusable start) or 2 (refitted).
+    const double *refit_start;
+    const int *valid;
+    int *refit_code;
+    int first_max_iter;
 };
 
 enum { ACT_EVAL = 0, ACT_RETRY = 1, ACT_DONE = 2 };
@@ -939,7 +949,7 @@ __device__ void lm_step_wave(LMShared<F> &s, const FitArgs &fa, int H, int W)
     double utr = ur;
     bool proposed = false;
     if (action != ACT_DONE) {
-        if (t >= fa.max_iter) {
+        if (t >= s.max_iter) {
             status = GM_ST_MAXITER;
             action = ACT_DONE;
         } else {
@@ -1093,29 +1103,44 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             continue;
         }
         const Meta me = ba.meta[g];
-        if (tid == 0) {
-            load_u<F>(s, ma, fa.params + (int64_t)g * ma.p);
-            clamp_u<F>(s.u, me.h, me.w);
-            for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
-            s.t = -1;             // -1: the next evaluation is the start point
-            s.status = GM_ST_MAXITER;
-            s.lambda = fa.lambda0;
-            s.fresh = 1;
-            s.apd = 0;
-            s.chi2 = 0.0;
-            s.action = ACT_EVAL;
-            for (int k = 0; k < F::P; ++k) {
-                s.Dg[k] = 1.0;
-                s.sig[k] = 1.0;
+        // phase 0: the fit from params; phase 1: the refit from refit_start
+        const bool refit = fa.refit_start != nullptr;
+        const int first = (refit && fa.valid && uniform(fa.valid[g]) == 0) ? 1 : 0;
+        int t0 = 0;
+        for (int phase = first; phase < 2; ++phase) {
+            if (tid == 0) {
+                load_u<F>(s, ma, (phase ? fa.refit_start : fa.params) + (int64_t)g * ma.p);
+                clamp_u<F>(s.u, me.h, me.w);
+                for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
+                s.t = -1;             // -1: the next evaluation is the start point
+                s.status = GM_ST_MAXITER;
+                s.max_iter = (refit && phase == 0) ? fa.first_max_iter : fa.max_iter;
+                s.lambda = fa.lambda0;
+                s.fresh = 1;
+                s.apd = 0;
+                s.chi2 = 0.0;
+                s.action = ACT_EVAL;
+                for (int k = 0; k < F::P; ++k) {
+                    s.Dg[k] = 1.0;
+                    s.sig[k] = 1.0;
+                }
             }
-        }
-        __syncthreads();
-        // one evaluation site: the start point first, then one trial per pass
-        while (s.action != ACT_DONE) {
-            if (s.action == ACT_EVAL)
-                evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
-            if (tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
             __syncthreads();
+            // one evaluation site: the start point first, then one trial per pass
+            while (s.action != ACT_DONE) {
+                if (s.action == ACT_EVAL)
+                    evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
+                if (tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
+                __syncthreads();
+            }
+            if (phase == 0) {
+                if (!refit || uniform(s.status) == GM_ST_CONVERGED) {
+                    t0 = -1;          // no refit
+                    break;
+                }
+                t0 = uniform(s.t);
+                __syncthreads();      // every thread has read s before thread 0 reloads it
+            }
         }
         if (tid == 0) {
             double nat[F::P];
@@ -1124,8 +1149,9 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             for (int k = 0; k < F::P; ++k)
                 if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
             fa.chi2[g] = s.chi2;
-            fa.niter[g] = s.t;
+            fa.niter[g] = s.t + (t0 > 0 ? t0 : 0);
             fa.status[g] = s.status;
+            if (fa.refit_code) fa.refit_code[g] = t0 < 0 ? 0 : (first ? 1 : 2);
             if (fa.err)
                 fit_errors<F>(s.A, s.g, s.u, s.freev, ma, fa.err + (int64_t)g * ma.p,
                               reinterpret_cast<double *>(planes));

@@ -69,6 +69,14 @@ struct CallInfo {
     int wpc = 0;          // persistent workgroups per CU (0: as many as are resident)
 };
 
+// Refit of the galaxies whose first fit does not converge (FitArgs).
+struct Refit {
+    const double *start;      // [n_gal][p] start of the refit
+    const int *valid;         // nullable: 0 = the first start is unusable
+    int *code;                // nullable: 0 / 1 / 2 per galaxy
+    int first_max_iter;       // trials of the first fit
+};
+
 // Device workspace of one call: [meta | extra | queue counter].
 struct Staged {
     Meta *meta;
@@ -205,7 +213,7 @@ int check_lds(int K, size_t *lds)
 
 template <class F, int NG, int... KTS>
 int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params, double *chi2, int32_t *niter,
-            int32_t *status, hipStream_t st)
+            int32_t *status, const Refit *rf, hipStream_t st)
 {
     const gm_batch *b = ci.b;
     size_t lds;
@@ -238,6 +246,12 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     fa.max_iter = o ? o->max_iter : 100;
     fa.lambda0 = o ? o->lambda0 : 1e-3;
     fa.tol = o ? o->step_tol : 1e-4;
+    if (rf) {
+        fa.refit_start = rf->start;
+        fa.valid = rf->valid;
+        fa.refit_code = rf->code;
+        fa.first_max_iter = rf->first_max_iter;
+    }
     return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
 }
 
@@ -331,7 +345,7 @@ struct Variant {
     int ng = 0;
     size_t (*lds)(int K) = nullptr;     // LDS bytes per workgroup at PSF side K
     int (*fit)(gm_ctx *, const CallInfo &, const gm_fit_opts *, double *, double *, int32_t *, int32_t *,
-               hipStream_t) = nullptr;
+               const Refit *, hipStream_t) = nullptr;
     int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t) = nullptr;
     int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t) = nullptr;
     int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t) = nullptr;

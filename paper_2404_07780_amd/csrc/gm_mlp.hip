@@ -387,26 +387,6 @@ __global__ void decode_kernel(int n_gal, ModelArgs ma, const Meta *meta, const f
     valid[g] = ok ? 1 : 0;
 }
 
-// ------------------------------------------------ fallback bookkeeping --
-__global__ void fallback_kernel(int n_gal, int p, const int *valid, const int *status, const double *pdef,
-                                double *params, int *active2, const int *niter, int *nsave, int *fallback)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_gal) return;
-    const bool fb = !valid[g] || status[g] != GM_ST_CONVERGED;
-    if (fb)
-        for (int k = 0; k < p; ++k) params[(int64_t)g * p + k] = pdef[(int64_t)g * p + k];
-    active2[g] = fb ? 1 : 0;
-    nsave[g] = fb && valid[g] ? niter[g] : 0;
-    if (fallback) fallback[g] = !valid[g] ? 1 : (fb ? 2 : 0);
-}
-
-__global__ void add_iters_kernel(int n_gal, const int *nsave, int *niter)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n_gal) niter[g] += nsave[g];
-}
-
 // ------------------------------------------------ synthetic noise -------
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
 // 32 x 32 -> 64-bit multiplications with a Weyl-sequence key schedule.
@@ -758,12 +738,15 @@ size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t learned_ws_bytes(const gm_mlp *mlp, int n, int p)
 {
     return al256((size_t)n * kInDim * 2) + al256((size_t)n * 8 * 8) + al256((size_t)n * mlp->out_dim * 4) +
-           2 * al256((size_t)n * mlp->hidden * 2) + al256((size_t)n * p * 8) + 3 * al256((size_t)n * 4) + 256;
+           2 * al256((size_t)n * mlp->hidden * 2) + al256((size_t)n * p * 8) + al256((size_t)n * 4) + 256;
 }
 
 // The learned-start fit on the context's MLP workspace (already sized by
-// learned_ws_bytes): moment guess, features, network, decoding, LM from the
-// valid proposals, then LM from the moment guess where needed.
+// learned_ws_bytes): moment guess, features, network, decoding, then one LM
+// launch from the valid proposals in which every galaxy whose proposal is
+// invalid or whose fit from it does not converge within the trial budget is
+// refitted from the moment guess by the same workgroup.  events (nullable):
+// before the moment guess, before and after the LM launch, at the end.
 int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *mlp, const gm_fit_opts *opts,
                 double *params_out, double *chi2_out, int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,
                 void *const *events, hipStream_t st)
@@ -777,10 +760,10 @@ int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *
     uint16_t *act1 = cv.take<uint16_t>((size_t)n * mlp->hidden);
     double *pdef = cv.take<double>((size_t)n * p);
     int *valid = cv.take<int>(n);
-    int *active2 = cv.take<int>(n);
-    int *nsave = cv.take<int>(n);
-    // default guess (the fallback start), features, proposal
-    int rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
+    int rc = mark_event(ctx, events, 0, st);
+    if (rc) return rc;
+    // default guess (the refit start), features, proposal
+    rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
     if (rc) return rc;
     rc = features_launch(ctx, mt, x, kInDim, mom8, st);
     if (rc) return rc;
@@ -790,27 +773,16 @@ int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *
     if (rc) return rc;
     rc = decode_launch(ctx, mt, out, mlp->out_dim, mom8, params_out, valid, st);
     if (rc) return rc;
-    // LM from the valid proposals
+    // LM from the valid proposals, refits from the moment guess in place
     gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
-    const int full_iter = o.max_iter;
-    if (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) o.max_iter = o.proposal_max_iter;
-    o.active = valid;
-    if ((rc = mark_event(ctx, events, 0, st))) return rc;
-    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
-    if (rc) return rc;
+    o.active = nullptr;
+    Refit rf{pdef, valid, fallback_out,
+             (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) ? o.proposal_max_iter : o.max_iter};
     if ((rc = mark_event(ctx, events, 1, st))) return rc;
-    // invalid or unconverged: refit from the default guess
-    hipLaunchKernelGGL(fallback_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p, valid, status_out, pdef,
-                       params_out, active2, niter_out, nsave, fallback_out);
-    if (hipGetLastError() != hipSuccess) return GM_EHIP;
-    o.active = active2;
-    o.max_iter = full_iter;
-    if ((rc = mark_event(ctx, events, 2, st))) return rc;
-    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, st);
+    rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, &rf, st);
     if (rc) return rc;
-    if ((rc = mark_event(ctx, events, 3, st))) return rc;
-    hipLaunchKernelGGL(add_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, nsave, niter_out);
-    return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
+    if ((rc = mark_event(ctx, events, 2, st))) return rc;
+    return mark_event(ctx, events, 3, st);
 }
 
 }  // namespace

@@ -187,6 +187,26 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                     const double *params, double *err_out, double *cov_out, void *stream);
 
+/* Bootstrap errors.  Sec. 5.2 names the bootstrap as the alternative to the
+ * covariance errors without fixing what is resampled; this library's reading
+ * is the Poisson bootstrap of the pixels.  Replica r of galaxy g multiplies
+ * every pixel weight Omega / sigma^2 by w ~ Poisson(1): w = the number of
+ * thresholds T_k <= x, T_k = floor(2^32 F(k)) for k = 0..11 with
+ * F(k) = e^-1 sum_{j<=k} 1/j! summed in that order in FP64, x the word
+ * (pixel mod 4) of Philox4x32-10 (Salmon et al. 2011) keyed by (seed low
+ * word, seed high word) with counter {pixel / 4, g, r, 1} (pixel: row-major
+ * index in the cutout).  Every replica is fitted by LM from params (device
+ * [n_gal][p], normally the fit) with opts (opts->active and err_out are
+ * ignored).  err_out (device [n_gal][p]): the sample standard deviation over
+ * the replicas that end GM_ST_CONVERGED, position angles as differences from
+ * params wrapped into (-90, 90]; NaN with fewer than two.  rep_params_out
+ * (nullable, device [n_gal][n_boot][p]) and rep_status_out (nullable, device
+ * [n_gal][n_boot]) receive the replica fits.  2 <= n_boot, n_gal n_boot <=
+ * 2^30; the replicas share the galaxies' pixels (nothing is copied). */
+int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
+                 const double *params, int32_t n_boot, uint64_t seed, double *err_out,
+                 double *rep_params_out, int32_t *rep_status_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal.  The paper motivates learned parameter estimators
  * (Sec. 1) and names the hand-chosen initial parameters as a limitation of

@@ -512,6 +512,57 @@ __global__ void copy_f64_kernel(const double *src, double *dst, int64_t n)
     if (i < n) dst[i] = src[i];
 }
 
+// dst[(g nb + r) p + k] = src[g p + k]: every replica starts at its galaxy's params
+__global__ void replicate_kernel(const double *src, double *dst, int n_gal, int nb, int p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_gal * nb * p) return;
+    const int64_t fit = i / p, k = i - fit * p;
+    dst[i] = src[(fit / nb) * p + k];
+}
+
+// Bootstrap standard deviation of column k of galaxy g over its replicas that
+// converged: sample standard deviation (two passes, replicas in order) of the
+// differences from params[g][k], wrapped into (-90, 90] for position angles.
+__global__ void boot_reduce_kernel(int n_gal, int nb, int p, uint32_t pa_mask, const double *params,
+                                   const double *rep, const int *status, double *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_gal * p) return;
+    const int64_t g = i / p;
+    const int k = (int)(i - g * p);
+    const bool pa = (pa_mask >> k) & 1u;
+    const double ref = params[i];
+    auto diff = [&](int r) {
+        double d = rep[(g * nb + r) * p + k] - ref;
+        if (pa) {
+            d = fmod(d, 180.0);
+            if (d > 90.0) d -= 180.0;
+            if (d <= -90.0) d += 180.0;
+        }
+        return d;
+    };
+    int m = 0;
+    double sum = 0.0;
+    for (int r = 0; r < nb; ++r)
+        if (status[g * nb + r] == GM_ST_CONVERGED) {
+            sum += diff(r);
+            ++m;
+        }
+    if (m < 2) {
+        err[i] = NAN;
+        return;
+    }
+    const double mean = sum / m;
+    double ss = 0.0;
+    for (int r = 0; r < nb; ++r)
+        if (status[g * nb + r] == GM_ST_CONVERGED) {
+            const double e = diff(r) - mean;
+            ss += e * e;
+        }
+    err[i] = sqrt(ss / (m - 1));
+}
+
 }  // namespace
 
 extern "C" {
@@ -667,6 +718,60 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     const Variant *v;
     if ((rc = pick_variant(ctx, mt, &v))) return rc;
     return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, nullptr, (hipStream_t)stream);
+}
+
+int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
+                 const double *params, int32_t n_boot, uint64_t seed, double *err_out, double *rep_params_out,
+                 int32_t *rep_status_out, void *stream)
+{
+    Match mt;
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0))) return GM_EINVAL;
+    if (n_boot < 2 || (int64_t)batch->n_gal * n_boot > (1 << 30)) return GM_EINVAL;
+    if (batch->n_gal == 0) return GM_OK;
+    if (!params || !err_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const int n = batch->n_gal, p = model->p;
+    const int64_t nfit = (int64_t)n * n_boot;
+    // position-angle columns
+    const int pa_slot[8] = {-1, 6, 5, 5, 6, 5, 5, -1};
+    uint32_t pa_mask = 0;
+    for (int c = 0; c < model->n_comp; ++c) {
+        const int sl = pa_slot[model->comp[c].type];
+        if (sl >= 0 && model->comp[c].param_index[sl] >= 0) pa_mask |= 1u << model->comp[c].param_index[sl];
+    }
+    // replica parameters, chi^2, trials and status in the context's scratch
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t need = al(sizeof(double) * nfit * p) + al(sizeof(double) * nfit) + 2 * al(sizeof(int) * nfit);
+    void *ws = nullptr;
+    if ((rc = ensure_aux(ctx, need, &ws))) return rc;
+    char *w8 = reinterpret_cast<char *>(ws);
+    double *rp = rep_params_out ? rep_params_out : reinterpret_cast<double *>(w8);
+    w8 += al(sizeof(double) * nfit * p);
+    double *chi2 = reinterpret_cast<double *>(w8);
+    w8 += al(sizeof(double) * nfit);
+    int *niter = reinterpret_cast<int *>(w8);
+    w8 += al(sizeof(int) * nfit);
+    int *rs = rep_status_out ? rep_status_out : reinterpret_cast<int *>(w8);
+    const int64_t cnt = nfit * p;
+    hipLaunchKernelGGL(replicate_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, params, rp, n,
+                       (int)n_boot, p);
+    if ((rc = hip_rc(hipGetLastError()))) return rc;
+    gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
+    o.active = nullptr;
+    o.err_out = nullptr;
+    FitExtra ex;
+    ex.n_boot = n_boot;
+    ex.boot_seed = seed;
+    if ((rc = v->fit(ctx, mt.ci, &o, rp, chi2, niter, rs, &ex, st))) return rc;
+    const int64_t ne = (int64_t)n * p;
+    hipLaunchKernelGGL(boot_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, n, (int)n_boot, p,
+                       pa_mask, params, rp, rs, err_out);
+    return hip_rc(hipGetLastError());
 }
 
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *params,

@@ -172,6 +172,55 @@ __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
     return b;
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32 x 32 -> 64-bit multiplications with a Weyl-sequence key schedule.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Poisson(1) deviate by inversion of a uniform 32-bit word: the number of
+// thresholds T_k <= x, T_k = floor(2^32 F(k)) for k = 0..11 with the CDF
+// F(k) = e^-1 sum_{j<=k} 1/j! summed in that order in FP64 (12 for the
+// remaining mass, below 1e-9).
+struct Poisson1Table {
+    uint32_t t[12];
+};
+__host__ __device__ constexpr Poisson1Table poisson1_table()
+{
+    Poisson1Table pt{};
+    double term = 0.36787944117144233;      // e^-1, correctly rounded
+    double cdf = term;
+    pt.t[0] = (uint32_t)(cdf * 4294967296.0);
+    for (int k = 1; k < 12; ++k) {
+        term = term / (double)k;
+        cdf = cdf + term;
+        pt.t[k] = (uint32_t)(cdf * 4294967296.0);
+    }
+    return pt;
+}
+__host__ __device__ inline int poisson1(uint32_t x)
+{
+    constexpr Poisson1Table T = poisson1_table();
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) k += (x >= T.t[j]) ? 1 : 0;
+    return k;
+}
+
 // ---------------------------------------------------------------- components
 // Orientation and oversampling window (rows wi0..wi1, cols wj0..wj1) of a
 // radial component.

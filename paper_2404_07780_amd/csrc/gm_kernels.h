@@ -464,12 +464,34 @@ __device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
     return ok ? 1.0f / (s * s) : 0.0f;
 }
 
+// A bootstrap replica (r >= 0) of galaxy g: every pixel weight is multiplied
+// by a Poisson(1) deviate drawn from Philox4x32-10 keyed by (k0, k1), counter
+// {pixel / 4, g, r, 1}, word pixel mod 4 (pixel: row-major index in the
+// cutout).  r < 0: the plain weights.
+struct BootArgs {
+    uint32_t k0, k1;
+    int g, r;
+};
+
+// Poisson(1) multipliers of the four consecutive pixels pix0 .. pix0 + 3.
+__device__ inline void boot_weights(const BootArgs &bt, int64_t pix0, float (&m)[4])
+{
+    const uint32_t q0 = (uint32_t)(pix0 >> 2), off = (uint32_t)(pix0 & 3);
+    const U4 a = philox4x32_10(U4{q0, (uint32_t)bt.g, (uint32_t)bt.r, 1u}, bt.k0, bt.k1);
+    U4 b = a;
+    if (off != 0) b = philox4x32_10(U4{q0 + 1u, (uint32_t)bt.g, (uint32_t)bt.r, 1u}, bt.k0, bt.k1);
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) m[t] = (float)poisson1(w[off + t]);
+}
+
 // One model evaluation at u (LDS): chi^2, g = J^T W r and A = J^T W J
 // (internal LM variables), written to out_chi2/out_g/out_A (LDS, A full
 // P x P).  All threads of the workgroup call it.
 template <class F, int KT, int NG>
 __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &ba, const Meta &me, EvalShared<F> &sh,
-                         float *planes, double *out_chi2, double *out_g, double *out_A)
+                         float *planes, double *out_chi2, double *out_g, double *out_A,
+                         const BootArgs &bt = BootArgs{0u, 0u, 0, -1})
 {
     constexpr int P = F::P;
     constexpr int NR = 1 + P + P * (P + 1) / 2;
@@ -495,13 +517,15 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
             tile_planes<F, KT, NG>(sh, planes, H, W, K, ti0, tj0, psf, r, cg, acc0, acc);
             const int i = ti0 + r;
             if (i < H) {
+                float bw[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                if (bt.r >= 0) boot_weights(bt, (int64_t)i * W + tj0 + 4 * cg, bw);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int j = tj0 + 4 * cg + t;
                     if (j >= W) continue;
                     const int64_t idx = me.img_off + (int64_t)i * W + j;
                     float d;
-                    const float wgt = pixel_weight(ba, idx, d);
+                    const float wgt = pixel_weight(ba, idx, d) * bw[t];
                     if (wgt == 0.0f) continue;
                     const double res = (double)d - (acc0[t] + sky);
                     c2 = fma((double)wgt * res, res, c2);
@@ -789,6 +813,10 @@ struct FitArgs {
     const int *valid;
     int *refit_code;
     int first_max_iter;
+    // Bootstrap (n_boot > 0): fit index i is replica i % n_boot of galaxy
+    // i / n_boot (BootArgs, key (boot_k0, boot_k1)); n_gal counts fit indices.
+    int n_boot;
+    uint32_t boot_k0, boot_k1;
 };
 
 enum { ACT_EVAL = 0, ACT_RETRY = 1, ACT_DONE = 2 };
@@ -1102,7 +1130,9 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             __syncthreads();      // s.gal is rewritten by thread 0 next
             continue;
         }
-        const Meta me = ba.meta[g];
+        const int src = fa.n_boot > 0 ? g / fa.n_boot : g;
+        const BootArgs bt{fa.boot_k0, fa.boot_k1, src, fa.n_boot > 0 ? g - src * fa.n_boot : -1};
+        const Meta me = ba.meta[src];
         // phase 0: the fit from params; phase 1: the refit from refit_start
         const bool refit = fa.refit_start != nullptr;
         const int first = (refit && fa.valid && uniform(fa.valid[g]) == 0) ? 1 : 0;
@@ -1129,7 +1159,7 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             // one evaluation site: the start point first, then one trial per pass
             while (s.action != ACT_DONE) {
                 if (s.action == ACT_EVAL)
-                    evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At);
+                    evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At, bt);
                 if (tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
                 __syncthreads();
             }

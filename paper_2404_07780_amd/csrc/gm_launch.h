@@ -69,12 +69,15 @@ struct CallInfo {
     int wpc = 0;          // persistent workgroups per CU (0: as many as are resident)
 };
 
-// Refit of the galaxies whose first fit does not converge (FitArgs).
-struct Refit {
-    const double *start;      // [n_gal][p] start of the refit
-    const int *valid;         // nullable: 0 = the first start is unusable
-    int *code;                // nullable: 0 / 1 / 2 per galaxy
-    int first_max_iter;       // trials of the first fit
+// Optional parts of a fit launch (FitArgs): the refit of galaxies whose first
+// fit does not converge, and bootstrap replicas.
+struct FitExtra {
+    const double *refit_start = nullptr;   // [n_gal][p] start of the refit
+    const int *valid = nullptr;            // nullable: 0 = the first start is unusable
+    int *refit_code = nullptr;             // nullable: 0 / 1 / 2 per galaxy
+    int first_max_iter = 0;                // trials of the first fit
+    int n_boot = 0;                        // > 0: n_boot replicas of each galaxy
+    uint64_t boot_seed = 0;
 };
 
 // Device workspace of one call: [meta | extra | queue counter].
@@ -213,30 +216,33 @@ int check_lds(int K, size_t *lds)
 
 template <class F, int NG, int... KTS>
 int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params, double *chi2, int32_t *niter,
-            int32_t *status, const Refit *rf, hipStream_t st)
+            int32_t *status, const FitExtra *ex, hipStream_t st)
 {
     const gm_batch *b = ci.b;
     size_t lds;
     int rc = check_lds<F, NG>(max_k(ci), &lds);
     if (rc) return rc;
+    // fit indices: the galaxies, or n_boot replicas of each (i -> galaxy i / n_boot)
+    const int nb = (ex && ex->n_boot > 0) ? ex->n_boot : 1;
+    const int nfit = b->n_gal * nb;
     // longest-processing-time order: biggest cutouts (times PSF area) first
-    std::vector<int> order(b->n_gal);
+    std::vector<int> order(nfit);
     std::iota(order.begin(), order.end(), 0);
     std::vector<double> cost(b->n_gal);
     for (int g = 0; g < b->n_gal; ++g) {
         double k = ci.convolved ? b->psf_k[g] : 1.0;
         cost[g] = (double)b->h[g] * b->w[g] * k * k;
     }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x / nb] > cost[y / nb]; });
     Staged sg;
-    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)b->n_gal, st, &sg);
+    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)nfit, st, &sg);
     if (rc) return rc;
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
     if (hipGetLastError() != hipSuccess) return GM_EHIP;
     FitArgs fa{};
     fa.order = reinterpret_cast<const int *>(sg.extra);
     fa.active = o ? o->active : nullptr;
-    fa.n_gal = b->n_gal;
+    fa.n_gal = nfit;
     fa.queue = sg.queue;
     fa.params = params;
     fa.chi2 = chi2;
@@ -246,11 +252,14 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     fa.max_iter = o ? o->max_iter : 100;
     fa.lambda0 = o ? o->lambda0 : 1e-3;
     fa.tol = o ? o->step_tol : 1e-4;
-    if (rf) {
-        fa.refit_start = rf->start;
-        fa.valid = rf->valid;
-        fa.refit_code = rf->code;
-        fa.first_max_iter = rf->first_max_iter;
+    if (ex) {
+        fa.refit_start = ex->refit_start;
+        fa.valid = ex->valid;
+        fa.refit_code = ex->refit_code;
+        fa.first_max_iter = ex->first_max_iter;
+        fa.n_boot = ex->n_boot;
+        fa.boot_k0 = (uint32_t)ex->boot_seed;
+        fa.boot_k1 = (uint32_t)(ex->boot_seed >> 32);
     }
     return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
 }
@@ -345,7 +354,7 @@ struct Variant {
     int ng = 0;
     size_t (*lds)(int K) = nullptr;     // LDS bytes per workgroup at PSF side K
     int (*fit)(gm_ctx *, const CallInfo &, const gm_fit_opts *, double *, double *, int32_t *, int32_t *,
-               const Refit *, hipStream_t) = nullptr;
+               const FitExtra *, hipStream_t) = nullptr;
     int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t) = nullptr;
     int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t) = nullptr;
     int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t) = nullptr;

@@ -388,26 +388,6 @@ __global__ void decode_kernel(int n_gal, ModelArgs ma, const Meta *meta, const f
 }
 
 // ------------------------------------------------ synthetic noise -------
-// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
-// 32 x 32 -> 64-bit multiplications with a Weyl-sequence key schedule.
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
-{
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
 // Box-Muller on two 32-bit words: u1 in (0, 1], u2 in [0, 1).
 __device__ inline void box_muller(uint32_t a, uint32_t b, double &z0, double &z1)
 {
@@ -776,8 +756,12 @@ int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *
     // LM from the valid proposals, refits from the moment guess in place
     gm_fit_opts o = opts ? *opts : gm_fit_opts{100, 1e-3, 1e-4, nullptr, 0, nullptr};
     o.active = nullptr;
-    Refit rf{pdef, valid, fallback_out,
-             (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) ? o.proposal_max_iter : o.max_iter};
+    FitExtra rf;
+    rf.refit_start = pdef;
+    rf.valid = valid;
+    rf.refit_code = fallback_out;
+    rf.first_max_iter =
+        (o.proposal_max_iter > 0 && o.proposal_max_iter < o.max_iter) ? o.proposal_max_iter : o.max_iter;
     if ((rc = mark_event(ctx, events, 1, st))) return rc;
     rc = var->fit(ctx, mt.ci, &o, params_out, chi2_out, niter_out, status_out, &rf, st);
     if (rc) return rc;

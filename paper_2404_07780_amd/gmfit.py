@@ -28,7 +28,8 @@ SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_j
            "gm_schedule_options", "gm_mlp_param_count", "gm_mlp_sync",
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise",
-           "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch", "gm_plan_elapsed", "gm_plan_destroy")
+           "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch", "gm_plan_elapsed", "gm_plan_destroy",
+           "gm_bootstrap")
 
 
 class GmError(RuntimeError):
@@ -114,6 +115,7 @@ def lib() -> C.CDLL:
         L.gm_plan_fit.argtypes = [v, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
         L.gm_plan_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
         L.gm_plan_launch.argtypes = [v, v]
+        L.gm_bootstrap.argtypes = [v, p, p, p, v, i, u64, v, v, v, v]
         L.gm_plan_elapsed.argtypes = [v, v]
         L.gm_plan_destroy.argtypes = [v]
         L.gm_plan_destroy.restype = None
@@ -121,7 +123,7 @@ def lib() -> C.CDLL:
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise", "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch",
-                     "gm_plan_elapsed"):
+                     "gm_plan_elapsed", "gm_bootstrap"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -366,6 +368,25 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
     return params, chi2, niter, status
+
+
+def gm_bootstrap(model: Model, batch: Batch, params, n_boot: int = 100, seed: int = 0, max_iter: int = 100,
+                 lambda0: float = 1e-3, step_tol: float = 1e-4, want_replicas: bool = False,
+                 ctx: Optional[Context] = None):
+    """Poisson-bootstrap errors [n, p] (device); with want_replicas also the
+    replica fits [n, n_boot, p] and their status [n, n_boot]."""
+    ctx = ctx or context(batch.device.index)
+    pr = _params_dev(params, batch, model.p)
+    err = torch.empty(batch.n, model.p, dtype=torch.float64, device=batch.device)
+    rp = rs = None
+    if want_replicas:
+        rp = torch.empty(batch.n, n_boot, model.p, dtype=torch.float64, device=batch.device)
+        rs = torch.empty(batch.n, n_boot, dtype=torch.int32, device=batch.device)
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, 0, None)
+    m, b = model.c(), batch.c()
+    _check("gm_bootstrap", lib().gm_bootstrap(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(pr), int(n_boot),
+                                              int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(err), _ptr(rp), _ptr(rs), _stream()))
+    return (err, rp, rs) if want_replicas else err
 
 
 def gm_param_errors(model: Model, batch: Batch, params, want_cov: bool = False, ctx: Optional[Context] = None):

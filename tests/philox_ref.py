@@ -47,3 +47,37 @@ def galaxy_normals(seed: int, galaxy_index: int, npix: int):
     z0, z1 = box_muller(r[:, 0], r[:, 1])
     z2, z3 = box_muller(r[:, 2], r[:, 3])
     return np.stack([z0, z1, z2, z3], axis=1).ravel()[:npix]
+
+
+def poisson1_thresholds():
+    """T_k = floor(2^32 F(k)), k = 0..11, F(k) = e^-1 sum_{j<=k} 1/j! summed in
+    that order in FP64 (the library's documented inversion table)."""
+    term = np.float64(0.36787944117144233)
+    cdf = term
+    out = [int(np.floor(cdf * np.float64(4294967296.0)))]
+    for k in range(1, 12):
+        term = term / np.float64(k)
+        cdf = cdf + term
+        out.append(int(np.floor(cdf * np.float64(4294967296.0))))
+    return np.array(out, np.uint64)
+
+
+def poisson1(x):
+    """Poisson(1) deviates from uint32 words: the number of thresholds <= x."""
+    t = poisson1_thresholds()
+    x = np.asarray(x, np.uint64)
+    return (x[..., None] >= t).sum(axis=-1)
+
+
+def replica_weights(seed: int, galaxy: int, replica: int, npix: int):
+    """Poisson(1) pixel multipliers of bootstrap replica `replica` of galaxy
+    `galaxy`: counter {pixel // 4, galaxy, replica, 1}, word pixel mod 4, key
+    (seed low word, seed high word)."""
+    nq = (npix + 3) // 4
+    ctr = np.zeros((nq, 4), np.uint64)
+    ctr[:, 0] = np.arange(nq)
+    ctr[:, 1] = galaxy
+    ctr[:, 2] = replica
+    ctr[:, 3] = 1
+    r = philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+    return poisson1(r.reshape(-1)[:npix])

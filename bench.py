@@ -79,6 +79,9 @@ WORKLOADS = {
     "sersic64": dict(n=64, cfg="sersic64", seed=0,
                      desc="64 single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px on 15x15, sigma = 1 "
                           "Gaussian noise, LM from moment-based start"),
+    "bootstrap": dict(n=1024, cfg="sersic64", seed=2,
+                      desc="Poisson-bootstrap errors, 100 replicas, of 1024 held-out single-Sersic galaxies (64x64, "
+                           "Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise) from their LM fits"),
     "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
                       desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
                            "25x25, Poisson + read noise, LM from moment-based start"),
@@ -167,6 +170,124 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi:
     return cpu, parity
 
 
+def bootstrap_baseline(n_sample: int, n_boot: int, seed: int, boot_seed: int, gm: G.Model):
+    """FP64 oracle bootstrap of galaxies 0..n_sample-1 (images rendered and
+    noised on the host): the oracle's own fit from its moment start, then its
+    fits of every replica (pixel weights from the test-side Philox reference)
+    from that fit, on all host cores; the GPU bootstrap of the same galaxies
+    from the same (oracle) fit is judged against it replica by replica and by
+    its standard deviations."""
+    import oracle as O
+    from tests import philox_ref
+    from tests.gpu_helpers import oracle_batch, param_parity
+    from tests.oracle_models import from_spec
+
+    ncores = len(os.sched_getaffinity(0))
+    b = oracle_batch("sersic64", n_sample, seed=seed)
+    om = from_spec(b.model)
+    names = S.MODEL_SPECS[b.model]["names"]
+    ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma)
+    fit, _, _, fs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
+                                nthreads=ncores)
+    # replica batch: galaxy g's replicas r = 0..n_boot-1 at fit index g n_boot + r
+    npx = int(b.h[0]) * int(b.w[0])
+    t0 = time.perf_counter()
+    data = np.repeat(b.data.reshape(b.n, npx), n_boot, axis=0)
+    sig = np.repeat(b.sigma.reshape(b.n, npx), n_boot, axis=0).copy()
+    om_ = np.ones_like(sig, dtype=np.uint8)
+    for g in range(b.n):
+        for r in range(n_boot):
+            w = philox_ref.replica_weights(boot_seed, g, r, npx)
+            i = g * n_boot + r
+            sig[i] = np.where(w > 0, sig[i] / np.sqrt(np.maximum(w, 1)), sig[i])
+            om_[i] = w > 0
+    m = b.n * n_boot
+    off = np.arange(m, dtype=np.int64) * npx
+    hh = np.full(m, b.h[0], np.int32)
+    ww = np.full(m, b.w[0], np.int32)
+    rp, _, _, rs = O.fit_batch(om, hh, ww, off, data.ravel(), sig.astype(np.float32).ravel(),
+                               np.full(m, b.psf_k[0], np.int32), np.zeros(m, np.int64), b.psf_of(0).ravel(),
+                               np.repeat(fit, n_boot, axis=0), omega=om_.ravel(), nthreads=ncores)
+    dt = time.perf_counter() - t0
+    db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf)
+    gerr, grp, grs, _ = [t.cpu().numpy() for t in G.gm_bootstrap(gm, db, fit, n_boot=n_boot, seed=boot_seed,
+                                                                  want_replicas=True)]
+    grp, grs = grp.reshape(m, -1), grs.reshape(m)
+    both = (grs == 0) & (rs == 0)
+    npass = sum(int(param_parity(names, grp[i], rp[i], sky_sigma=float(np.median(sig[i])))[0].all())
+                for i in np.where(both)[0])
+    ipa = names.index("pa")
+    worst = 0.0
+    for g in range(b.n):
+        sel = slice(g * n_boot, (g + 1) * n_boot)
+        cv = rs[sel] == 0
+        if cv.sum() < 2 or not np.array_equal(cv, grs[sel] == 0):
+            continue
+        d = rp[sel][cv] - fit[g]
+        d[:, ipa] = (d[:, ipa] + 90.0) % 180.0 - 90.0
+        ref = d.std(axis=0, ddof=1)
+        worst = max(worst, float(np.max(np.abs(gerr[g] - ref) / ref)))
+    cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
+               sample=f"galaxies 0..{n_sample - 1} of the workload (rendered and noised on the host), {n_boot} "
+                      f"replicas each fitted from the oracle's fit, {dt:.1f} s")
+    parity = dict(sample=n_sample, replicas=m, both_converged=int(both.sum()), pass_1e4=int(npass),
+                  std_max_rel_diff=worst)
+    return cpu, parity
+
+
+def bootstrap_main(args, n: int, seed: int):
+    """--workload bootstrap: one step = gm_bootstrap (100 replicas) of the batch
+    from its plain LM fit (made before the timed region)."""
+    from paper_2404_07780_amd import tune
+
+    nb = args.n_boot
+    b, gm, db = make_batch("sersic64", n, seed)
+    tune.apply(gm, db, sample=n, trials=0)
+    plan = G.gm_plan_fit(gm, db, errors=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    fit = plan.params.clone()
+    dev, p = db.device, gm.p
+    out = (torch.empty(n, p, dtype=torch.float64, device=dev), torch.empty(n, nb, p, dtype=torch.float64, device=dev),
+           torch.empty(n, nb, dtype=torch.int32, device=dev), torch.empty(n, nb, dtype=torch.int32, device=dev))
+    boot_seed = 0x5EED
+
+    def step(ev):
+        if ev:
+            ev[0].record()
+        G.gm_bootstrap(gm, db, fit, n_boot=nb, seed=boot_seed, out=out)
+        if ev:
+            ev[1].record()
+
+    wall, evs = timed(step, args.steps, args.warmup, "bootstrap")
+    ms = float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)]))
+    rn, rs = out[3].cpu().numpy().astype(np.float64), out[2].cpu().numpy()
+    f_conv, f_red = flops_per_eval(b, p, p - 1)
+    flops = float(np.sum((f_conv + f_red)[:, None] * (1.0 + rn) * (rs != G.ST_NONFINITE)))
+    achieved = flops / (ms / 1e3) / 1e12
+    cpu = parity = None
+    if args.cpu_sample != 0:
+        ns = 8 if args.cpu_sample is None else args.cpu_sample
+        log(f"cpu baseline: oracle bootstrap of {ns} galaxies x {nb} replicas")
+        cpu, parity = bootstrap_baseline(ns, nb, seed, boot_seed, gm)
+    outj = {
+        "metric": "galaxies bootstrapped/s (Poisson bootstrap, LM fit per replica)",
+        "value": n / (wall / args.steps), "unit": "galaxies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"bootstrap: {WORKLOADS['bootstrap']['desc']}", "n_gal": n, "seed": seed,
+                   "n_boot": nb, "replica_fits_per_s": n * nb / (wall / args.steps)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "lm_fit_kernel over the replicas (with the replication and reduction kernels)",
+                     "kernel_ms": ms, "flops_per_step": flops},
+        "replicas": {"mean_trials": float(rn.mean()), "converged": float(np.mean(rs == G.ST_CONVERGED))},
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(outj))
+
+
 def timed(step, steps: int, warmup: int, name: str):
     for i in range(warmup):
         step(None)
@@ -249,6 +370,7 @@ def main():
                          "(-1 = the whole batch, 0 = library default schedule)")
     ap.add_argument("--eager", action="store_true",
                     help="time the eager calls instead of replays of the captured plans")
+    ap.add_argument("--n-boot", type=int, default=100, help="replicas per galaxy (bootstrap workload)")
     ap.add_argument("--calib", action="store_true",
                     help="first run one 1 GiB device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -270,6 +392,8 @@ def main():
     wl = WORKLOADS[args.workload]
     n = args.n or wl["n"]
     seed = wl["seed"] if args.seed is None else args.seed
+    if args.workload == "bootstrap":
+        return bootstrap_main(args, n, seed)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
         args.cpu_sample = {"learned": 2048, "sersic64": 64}.get(args.workload, 160)

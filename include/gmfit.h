@@ -200,12 +200,13 @@ int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
  * ignored).  err_out (device [n_gal][p]): the sample standard deviation over
  * the replicas that end GM_ST_CONVERGED, position angles as differences from
  * params wrapped into (-90, 90]; NaN with fewer than two.  rep_params_out
- * (nullable, device [n_gal][n_boot][p]) and rep_status_out (nullable, device
- * [n_gal][n_boot]) receive the replica fits.  2 <= n_boot, n_gal n_boot <=
+ * (nullable, device [n_gal][n_boot][p]), rep_status_out and rep_niter_out
+ * (nullable, device [n_gal][n_boot]) receive the replica fits.  2 <= n_boot, n_gal n_boot <=
  * 2^30; the replicas share the galaxies' pixels (nothing is copied). */
 int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
                  const double *params, int32_t n_boot, uint64_t seed, double *err_out,
-                 double *rep_params_out, int32_t *rep_status_out, void *stream);
+                 double *rep_params_out, int32_t *rep_status_out, int32_t *rep_niter_out,
+                 void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned proposal.  The paper motivates learned parameter estimators

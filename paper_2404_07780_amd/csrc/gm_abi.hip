@@ -722,7 +722,7 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
 
 int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
                  const double *params, int32_t n_boot, uint64_t seed, double *err_out, double *rep_params_out,
-                 int32_t *rep_status_out, void *stream)
+                 int32_t *rep_status_out, int32_t *rep_niter_out, void *stream)
 {
     Match mt;
     int rc = prologue(ctx, model, batch, mt);
@@ -754,7 +754,7 @@ int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     w8 += al(sizeof(double) * nfit * p);
     double *chi2 = reinterpret_cast<double *>(w8);
     w8 += al(sizeof(double) * nfit);
-    int *niter = reinterpret_cast<int *>(w8);
+    int *niter = rep_niter_out ? rep_niter_out : reinterpret_cast<int *>(w8);
     w8 += al(sizeof(int) * nfit);
     int *rs = rep_status_out ? rep_status_out : reinterpret_cast<int *>(w8);
     const int64_t cnt = nfit * p;

@@ -115,7 +115,7 @@ def lib() -> C.CDLL:
         L.gm_plan_fit.argtypes = [v, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
         L.gm_plan_fit_learned.argtypes = [v, p, p, p, p, v, v, v, v, v, v, i, C.POINTER(C.c_void_p)]
         L.gm_plan_launch.argtypes = [v, v]
-        L.gm_bootstrap.argtypes = [v, p, p, p, v, i, u64, v, v, v, v]
+        L.gm_bootstrap.argtypes = [v, p, p, p, v, i, u64, v, v, v, v, v]
         L.gm_plan_elapsed.argtypes = [v, v]
         L.gm_plan_destroy.argtypes = [v]
         L.gm_plan_destroy.restype = None
@@ -372,21 +372,27 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
 
 def gm_bootstrap(model: Model, batch: Batch, params, n_boot: int = 100, seed: int = 0, max_iter: int = 100,
                  lambda0: float = 1e-3, step_tol: float = 1e-4, want_replicas: bool = False,
-                 ctx: Optional[Context] = None):
+                 ctx: Optional[Context] = None, out=None):
     """Poisson-bootstrap errors [n, p] (device); with want_replicas also the
-    replica fits [n, n_boot, p] and their status [n, n_boot]."""
+    replica fits [n, n_boot, p], their status and trials [n, n_boot].  `out`
+    may pass preallocated (err, rep_params, rep_status, rep_niter)."""
     ctx = ctx or context(batch.device.index)
     pr = _params_dev(params, batch, model.p)
-    err = torch.empty(batch.n, model.p, dtype=torch.float64, device=batch.device)
-    rp = rs = None
-    if want_replicas:
-        rp = torch.empty(batch.n, n_boot, model.p, dtype=torch.float64, device=batch.device)
-        rs = torch.empty(batch.n, n_boot, dtype=torch.int32, device=batch.device)
+    if out is not None:
+        err, rp, rs, rn = out
+    else:
+        err = torch.empty(batch.n, model.p, dtype=torch.float64, device=batch.device)
+        rp = rs = rn = None
+        if want_replicas:
+            rp = torch.empty(batch.n, n_boot, model.p, dtype=torch.float64, device=batch.device)
+            rs = torch.empty(batch.n, n_boot, dtype=torch.int32, device=batch.device)
+            rn = torch.empty(batch.n, n_boot, dtype=torch.int32, device=batch.device)
     o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None, 0, None)
     m, b = model.c(), batch.c()
     _check("gm_bootstrap", lib().gm_bootstrap(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(pr), int(n_boot),
-                                              int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(err), _ptr(rp), _ptr(rs), _stream()))
-    return (err, rp, rs) if want_replicas else err
+                                              int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(err), _ptr(rp), _ptr(rs),
+                                              _ptr(rn), _stream()))
+    return (err, rp, rs, rn) if (want_replicas or out is not None) else err
 
 
 def gm_param_errors(model: Model, batch: Batch, params, want_cov: bool = False, ctx: Optional[Context] = None):

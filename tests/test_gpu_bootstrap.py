@@ -44,7 +44,7 @@ def test_bootstrap_replicas_match_oracle(cfg, n, nb):
     names = S.MODEL_SPECS[b.model]["names"]
     pa_cols = [k for k, nm in enumerate(names) if nm.startswith("pa")]
     start = b.truth.copy()
-    err, rp, rs = G.gm_bootstrap(gm, _dev(b), start, n_boot=nb, seed=SEED, want_replicas=True)
+    err, rp, rs, _ = G.gm_bootstrap(gm, _dev(b), start, n_boot=nb, seed=SEED, want_replicas=True)
     err, rp, rs = err.cpu().numpy(), rp.cpu().numpy(), rs.cpu().numpy()
     npass = nboth = 0
     for g in range(b.n):

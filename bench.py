@@ -82,6 +82,9 @@ WORKLOADS = {
     "bootstrap": dict(n=1024, cfg="sersic64", seed=2,
                       desc="Poisson-bootstrap errors, 100 replicas, of 1024 held-out single-Sersic galaxies (64x64, "
                            "Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise) from their LM fits"),
+    "paper": dict(n=8289, cfg="paper", seed=0,
+                  desc="the shapes of the paper's SDSS test: 8289 single-Sersic galaxies, 128x128, one Moffat PSF "
+                       "(beta 3, FWHM 3.03 px) on 41x41, Poisson + 5 e- read noise, LM from moment-based start"),
     "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
                       desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
                            "25x25, Poisson + read noise, LM from moment-based start"),
@@ -396,7 +399,7 @@ def main():
         return bootstrap_main(args, n, seed)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
-        args.cpu_sample = {"learned": 2048, "sersic64": 64}.get(args.workload, 160)
+        args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32}.get(args.workload, 160)
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()
@@ -535,6 +538,10 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
     }
+    if args.workload == "paper":
+        # the paper's own figure on its SDSS sample (different method, data and GPU): context only
+        out["context"] = {"paper_fits": 8289, "paper_seconds": 600, "paper_device": "one NVIDIA A100",
+                          "paper_galaxies_per_s": 8289 / 600.0, "paper_method": "gradient descent (torch)"}
     if learned:
         pl = results["plain"]
         out["plain_lm"] = dict(value=pl["value"], ms_per_step=pl["ms_per_step"], lm_ms=pl["lm_ms"],

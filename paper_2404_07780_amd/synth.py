@@ -20,7 +20,11 @@ Workloads (the distributions the fitter is benchmarked on):
     Moffat PSF per galaxy (beta 2.5-4.5, FWHM 1.2-2.5 px, 25x25), Poisson
     plus 5 e- read noise;
   * ``bulgedisk`` -- 128x128, Sersic bulge + exponential disk with a shared
-    centre, PSF and noise as ``uneven``.
+    centre, PSF and noise as ``uneven``;
+  * ``paper``     -- the shapes of the paper's SDSS test (Sec. 3): 128x128
+    single Sersic + sky, one circular Moffat PSF of beta 3 and FWHM 3.03 px
+    (1.2 arcsec at 0.396 arcsec/px) on 41x41, noise as ``uneven``; synthetic
+    galaxies of the common draw (no survey item is reproduced).
 Common Sersic draw: centre (W/2, H/2) + U(-2, 2) px, r_e log-uniform
 [2, 15] px, n U(0.5, 6), q U(0.3, 1), PA U(0, 180) deg, peak SNR
 log-uniform [20, 200] (peak of the noiseless convolved galaxy without sky
@@ -103,7 +107,7 @@ FLUX_COLUMNS = {
     "point": [("mag", 2)],
 }
 
-CONFIG_IDS = {"sersic64": 1, "uneven": 2, "bulgedisk": 3, "mixed": 5}
+CONFIG_IDS = {"sersic64": 1, "uneven": 2, "bulgedisk": 3, "mixed": 5, "paper": 6}
 
 
 def _rng(seed: int, cfg: int, i: int, stream: int) -> np.random.Generator:
@@ -207,6 +211,7 @@ def draw(config: str, n: int, seed: int = 0, start: int = 0) -> Batch:
     model = "bulgedisk" if config == "bulgedisk" else "sersic"
     p = MODEL_SPECS[model]["p"]
     gpsf = gaussian_psf(1.5, 15) if config == "sersic64" else None
+    ppsf = moffat_psf(3.0, 3.03, 41) if config == "paper" else None
     for i in range(start, start + n):
         r = _rng(seed, cfg, i, 0)
         t = np.zeros(p)
@@ -224,6 +229,12 @@ def draw(config: str, n: int, seed: int = 0, start: int = 0) -> Batch:
             fwhm = r.uniform(1.2, 2.5)
             sky = r.uniform(50.0, 200.0)
             psf = moffat_psf(beta, fwhm, 25)
+            t[:] = [x0, y0, M0, re, nn, q, pa, sky]
+        elif config == "paper":
+            h = w = 128
+            x0, y0, re, nn, q, pa, snr = _sersic_draw(r, h, w)
+            sky = r.uniform(50.0, 200.0)
+            psf = ppsf
             t[:] = [x0, y0, M0, re, nn, q, pa, sky]
         elif config == "bulgedisk":
             h = w = 128

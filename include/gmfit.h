@@ -60,8 +60,11 @@ enum {
  *   GM_GAUSSIAN x0 y0 I0 fwhm q pa          Sec. 4.2.4
  *   GM_MOFFAT   x0 y0 mag fwhm q pa beta    Sec. 4.2.5 (beta fixed)
  *   GM_SKY      sky                         Sec. 4.2.6, added after convolution
+ *   GM_SKYPLANE sky kx ky                   Appendix D, eq. (new_sky_I): the tilted-plane
+ *               sky + kx (x - W/2) + ky (y - H/2) about the cutout's centre, added after
+ *               convolution (compiled with a single Sersic; other models GM_EUNSUPPORTED)
  * Boxiness is 0 (r_box = 1, eq. (rbox)). */
-enum { GM_SERSIC = 1, GM_EXPDISK, GM_FERRER, GM_KING, GM_GAUSSIAN, GM_MOFFAT, GM_SKY };
+enum { GM_SERSIC = 1, GM_EXPDISK, GM_FERRER, GM_KING, GM_GAUSSIAN, GM_MOFFAT, GM_SKY, GM_SKYPLANE };
 
 typedef struct {
     int32_t type;             /* GM_SERSIC ... GM_SKY */

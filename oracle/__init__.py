@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
+SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 ST_CONVERGED, ST_MAXITER, ST_STALLED, ST_NONFINITE = 0, 1, 2, 3
 MAX_COMP, MAX_SLOTS, MAX_P = 4, 8, 16
 
@@ -36,6 +36,7 @@ SLOTS = {
     GAUSSIAN: ("x0", "y0", "I0", "fwhm", "q", "pa"),
     MOFFAT: ("x0", "y0", "mag", "fwhm", "q", "pa", "beta"),
     SKY: ("sky",),
+    SKYPLANE: ("sky", "kx", "ky"),
 }
 
 

@@ -174,9 +174,9 @@ double orc_sersic_db(double n)
  * natural log for every positive scale and for the Sersic index; radians for
  * the position angle (the paper's `log=True` / `angle=True` flags,
  * Appendix A, extended to the other scales). */
-enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE };
+enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE, K_SKYGRAD };
 
-static const int slot_kind[8][ORC_MAX_SLOTS] = {
+static const int slot_kind[9][ORC_MAX_SLOTS] = {
     /* 0 unused */ {0},
     /* SERSIC   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_N, K_Q, K_PA, K_NONE},
     /* EXPDISK  */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_NONE, K_NONE},
@@ -185,11 +185,12 @@ static const int slot_kind[8][ORC_MAX_SLOTS] = {
     /* GAUSSIAN */ {K_X0, K_Y0, K_AMP, K_SCALE, K_Q, K_PA, K_NONE, K_NONE},
     /* MOFFAT   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_SHAPE, K_NONE},
     /* SKY      */ {K_SKY, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE},
+    /* SKYPLANE */ {K_SKY, K_SKYGRAD, K_SKYGRAD, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE},
 };
 
 int orc_slot_kind(int type, int slot)
 {
-    if (type < 1 || type > 7 || slot < 0 || slot >= ORC_MAX_SLOTS)
+    if (type < 1 || type > 8 || slot < 0 || slot >= ORC_MAX_SLOTS)
         return -1;
     return slot_kind[type][slot];
 }
@@ -211,9 +212,9 @@ int orc_validate(const orc_model *m)
     int seen[ORC_MAX_P] = {0};
     for (int c = 0; c < m->ncomp; ++c) {
         const orc_comp *cp = &m->comp[c];
-        if (cp->type < ORC_SERSIC || cp->type > ORC_SKY)
+        if (cp->type < ORC_SERSIC || cp->type > ORC_SKYPLANE)
             return ORC_EINVAL;
-        if (cp->type == ORC_SKY && cp->convolve)
+        if ((cp->type == ORC_SKY || cp->type == ORC_SKYPLANE) && cp->convolve)
             return ORC_EINVAL;
         for (int s = 0; s < ORC_MAX_SLOTS; ++s) {
             int kind = slot_kind[cp->type][s], k = cp->idx[s];
@@ -283,6 +284,7 @@ typedef struct {
     /* others */
     double scale, scale2, a_f, b_f, alpha, beta, rd;
     double kA, dkA_dlnrc, dkA_dlnrt;   /* King: T^(-1/alpha) and derivatives */
+    double xc, yc;               /* plane sky: the cutout's geometric centre */
 } comp_prep;
 
 static void prep_component(const orc_model *m, int c, const double *params, comp_prep *cp)
@@ -291,7 +293,7 @@ static void prep_component(const orc_model *m, int c, const double *params, comp
     cp->type = m->comp[c].type;
     comp_values(m, c, params, cp->v);
     double *v = cp->v;
-    if (cp->type == ORC_SKY)
+    if (cp->type == ORC_SKY || cp->type == ORC_SKYPLANE)
         return;
     double th = v[5] * ORC_PI / 180.0;  /* PA slot is 5 for all but Sersic */
     double q = v[4];
@@ -359,6 +361,13 @@ static void comp_point(const comp_prep *cp, double x, double y, double *I, doubl
     if (cp->type == ORC_SKY) {
         *I = cp->v[0];
         dI[0] = 1.0;
+        return;
+    }
+    if (cp->type == ORC_SKYPLANE) {         /* Appendix D, eq. (new_sky_I) */
+        *I = cp->v[0] + cp->v[1] * (x - cp->xc) + cp->v[2] * (y - cp->yc);
+        dI[0] = 1.0;
+        dI[1] = x - cp->xc;
+        dI[2] = y - cp->yc;
         return;
     }
     /* rotate into the component frame (Sec. 4.1, B = 0) */
@@ -491,7 +500,7 @@ static void oversample_window(const orc_model *m, const comp_prep *cp, int h, in
                               int *i0, int *i1, int *j0, int *j1)
 {
     *i0 = 1; *i1 = 0; *j0 = 1; *j1 = 0;         /* empty */
-    if (cp->type == ORC_SKY || m->oversample <= 1 || m->os_window <= 0)
+    if (cp->type == ORC_SKY || cp->type == ORC_SKYPLANE || m->oversample <= 1 || m->os_window <= 0)
         return;
     int half = m->os_window / 2;
     double jcd = floor(cp->v[0]), icd = floor((double)h - cp->v[1]);
@@ -580,8 +589,11 @@ static int model_and_jacobian_u(const orc_model *m, int h, int w, const double *
 {
     int p = m->p, npix = h * w;
     comp_prep cps[ORC_MAX_COMP];
-    for (int c = 0; c < m->ncomp; ++c)
+    for (int c = 0; c < m->ncomp; ++c) {
         prep_component(m, c, params, &cps[c]);
+        cps[c].xc = 0.5 * w;
+        cps[c].yc = 0.5 * h;
+    }
     double *val = malloc(sizeof(double) * npix);
     double *tmp = malloc(sizeof(double) * npix);
     double *der = jac ? malloc(sizeof(double) * (size_t)p * npix) : NULL;
@@ -1075,7 +1087,7 @@ int orc_default_guess(const orc_model *m, int h, int w, const float *data, const
     }
     int nflux = 0, nrad = 0;
     for (int c = 0; c < m->ncomp; ++c) {
-        if (m->comp[c].type == ORC_SKY) continue;
+        if (m->comp[c].type == ORC_SKY || m->comp[c].type == ORC_SKYPLANE) continue;
         nrad++;
         if (m->comp[c].idx[2] >= 0) nflux++;
     }
@@ -1107,6 +1119,9 @@ int orc_default_guess(const orc_model *m, int h, int w, const float *data, const
             break;
         case ORC_SKY:
             v[0] = sky0;
+            break;
+        case ORC_SKYPLANE:
+            v[0] = sky0; v[1] = 0.0; v[2] = 0.0;
             break;
         }
         /* the first component to claim a column sets it (tied centres) */

@@ -12,7 +12,7 @@
 #define ORC_MAX_P 16
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESINGULAR = -3 };
-enum { ORC_SERSIC = 1, ORC_EXPDISK, ORC_FERRER, ORC_KING, ORC_GAUSSIAN, ORC_MOFFAT, ORC_SKY };
+enum { ORC_SERSIC = 1, ORC_EXPDISK, ORC_FERRER, ORC_KING, ORC_GAUSSIAN, ORC_MOFFAT, ORC_SKY, ORC_SKYPLANE };
 enum { ORC_ST_CONVERGED = 0, ORC_ST_MAXITER = 1, ORC_ST_STALLED = 2, ORC_ST_NONFINITE = 3 };
 
 /* One component.  Natural slots per type (PA in degrees):
@@ -23,6 +23,9 @@ enum { ORC_ST_CONVERGED = 0, ORC_ST_MAXITER = 1, ORC_ST_STALLED = 2, ORC_ST_NONF
  *   GAUSSIAN x0 y0 I0 fwhm q pa
  *   MOFFAT   x0 y0 mag fwhm q pa beta          (beta always fixed)
  *   SKY      sky
+ *   SKYPLANE sky kx ky: the tilted-plane sky of Appendix D, eq. (new_sky_I),
+ *            I = sky + kx (x - W/2) + ky (y - H/2) about the cutout's
+ *            geometric centre (pixel grid of Appendix C, y up); unconvolved
  * idx[s] is the column of the galaxy's parameter vector that holds slot s,
  * or -1 if the slot is fixed at fixed[s]; a column shared by several slots
  * ties them. */

@@ -286,12 +286,12 @@ namespace {
 
 // Natural slots per profile type (index = type) and the LM slots among them
 // (the trailing ones are shape constants that stay fixed).
-const int kSlots[8] = {0, 7, 6, 8, 8, 6, 7, 1};
-const int kLmSlots[8] = {0, 7, 6, 6, 7, 6, 6, 1};
+const int kSlots[9] = {0, 7, 6, 8, 8, 6, 7, 1, 3};
+const int kLmSlots[9] = {0, 7, 6, 6, 7, 6, 6, 1, 3};
 
 bool comp_ok(const gm_component &c, int p)
 {
-    if (c.type < GM_SERSIC || c.type > GM_SKY) return false;
+    if (c.type < GM_SERSIC || c.type > GM_SKYPLANE) return false;
     for (int s = 0; s < 8; ++s) {
         int k = c.param_index[s];
         if (s >= kSlots[c.type]) {
@@ -311,7 +311,10 @@ void take(const gm_component &c, int s, int k, ModelArgs &ma)
 }
 
 // Family tables (variants in order of preference), built once.
-enum { FAM_SERSIC = 1, FAM_EXPDISK, FAM_FERRER, FAM_KING, FAM_GAUSSIAN, FAM_MOFFAT, FAM_BULGEDISK, FAM_SERSICBAR };
+enum {
+    FAM_SERSIC = 1, FAM_EXPDISK, FAM_FERRER, FAM_KING, FAM_GAUSSIAN, FAM_MOFFAT, FAM_BULGEDISK, FAM_SERSICBAR,
+    FAM_SERSICTILT
+};
 
 FamilyOps family(int id, Variant a, Variant b)
 {
@@ -345,7 +348,10 @@ const FamilyOps *family_table(int id)
         family(FAM_MOFFAT, var_moffat_2()),
         family(FAM_BULGEDISK, var_bulgedisk_2(), var_bulgedisk_3()),
         family(FAM_SERSICBAR, var_sersicbar_2(), var_sersicbar_3()),
+        family(FAM_SERSICTILT, var_sersictilt_1(), var_sersictilt_2()),
     };
+    // indexed by id: the entries are in FAM_* order
+    static_assert(sizeof(tab) / sizeof(tab[0]) == FAM_SERSICTILT, "family table out of order");
     return &tab[id - 1];
 }
 
@@ -376,7 +382,7 @@ int match_model(const gm_model *m, Match &out)
     for (int i = 0; i < m->n_comp; ++i) {
         const gm_component &c = m->comp[i];
         if (!comp_ok(c, m->p)) return GM_EINVAL;
-        if (c.type == GM_SKY) {
+        if (c.type == GM_SKY || c.type == GM_SKYPLANE) {
             if (c.convolve) return GM_EINVAL;
             if (sky) return GM_EUNSUPPORTED;
             sky = &c;
@@ -417,12 +423,21 @@ int match_model(const gm_model *m, Match &out)
         int ns = kLmSlots[c.type];
         for (int s = 0; s < ns; ++s) take(c, s, s, ma);
         for (int s = ns; s < kSlots[c.type]; ++s) ma.cst[s - ns] = c.fixed[s];
-        if (sky) take(*sky, 0, ns, ma);
-        nint = ns + 1;
-        ops = single_ops(c.type);
+        if (sky && sky->type == GM_SKYPLANE) {
+            // the tilted-plane sky is compiled for a single Sersic
+            if (c.type != GM_SERSIC) return GM_EUNSUPPORTED;
+            for (int s = 0; s < 3; ++s) take(*sky, s, ns + s, ma);
+            nint = ns + 3;
+            ops = family_table(FAM_SERSICTILT);
+        } else {
+            if (sky) take(*sky, 0, ns, ma);
+            nint = ns + 1;
+            ops = single_ops(c.type);
+        }
     } else {
         // Sersic + (exponential disk | Ferrer) with a shared centre, both convolved
         const gm_component *a = rad[0], *b = rad[1];
+        if (sky && sky->type == GM_SKYPLANE) return GM_EUNSUPPORTED;
         if (b->type == GM_SERSIC) std::swap(a, b);
         if (a->type != GM_SERSIC || !(b->type == GM_EXPDISK || b->type == GM_FERRER) || !a->convolve ||
             !b->convolve)
@@ -448,6 +463,7 @@ int match_model(const gm_model *m, Match &out)
     out.ci.convolved = convolved;
     out.single_type = nrad == 1 ? rad[0]->type : 0;
     out.has_sky = sky != nullptr;
+    out.tilt = sky != nullptr && sky->type == GM_SKYPLANE;
     return GM_OK;
 }
 
@@ -738,7 +754,7 @@ int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     const int n = batch->n_gal, p = model->p;
     const int64_t nfit = (int64_t)n * n_boot;
     // position-angle columns
-    const int pa_slot[8] = {-1, 6, 5, 5, 6, 5, 5, -1};
+    const int pa_slot[9] = {-1, 6, 5, 5, 6, 5, 5, -1, -1};
     uint32_t pa_mask = 0;
     for (int c = 0; c < model->n_comp; ++c) {
         const int sl = pa_slot[model->comp[c].type];

@@ -20,7 +20,7 @@ constexpr float kDMag = -0.921034037197618f;   // d ln F / d m = -0.4 ln 10
 // Kinds of LM variables: centres, magnitudes, amplitudes, axis ratio and sky
 // are used as they are; positive scales and the Sersic index through their
 // natural log; position angles in radians (degrees at the interface).
-enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY };
+enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY, KSKYG };
 
 __host__ __device__ inline double nat_to_u(int kind, double p)
 {
@@ -730,27 +730,47 @@ struct Moffat {
 // an amplitude (dividing by it would fail at zero).
 
 // One component + sky: u = the component's slots, then sky.
-template <class C>
+// One radial component and a flat sky, or (TILT) the tilted-plane sky of
+// Appendix D, eq. (new_sky_I): sky + kx (x - W/2) + ky (y - H/2), whose two
+// gradient variables follow the sky in the LM vector.
+template <class C, bool TILT = false>
 struct FamSingle {
-    static constexpr int P = C::NS + 1, NCOMP = 1, NRAD = 1, SKY = C::NS, ND = C::NS;
+    static constexpr int P = C::NS + (TILT ? 3 : 1), NCOMP = 1, NRAD = 1, SKY = C::NS, ND = C::NS;
     static constexpr int DER = C::kind(2) == KMAG ? 2 : -1;
-    static constexpr int NPL = DER >= 0 ? P - 1 : P;
-    __host__ __device__ static constexpr int kind(int k) { return k < C::NS ? C::kind(k) : KSKY; }
+    static constexpr int NPL = 1 + C::NS - (DER >= 0 ? 1 : 0);
+    __host__ __device__ static constexpr int kind(int k)
+    {
+        return k < C::NS ? C::kind(k) : k == SKY ? KSKY : KSKYG;
+    }
     __host__ __device__ static constexpr int plane(int k)
     {
-        return (k == SKY || k == DER) ? -1 : (DER >= 0 && k > DER) ? k : k + 1;
+        return (k >= SKY || k == DER) ? -1 : (DER >= 0 && k > DER) ? k : k + 1;
+    }
+    // the sky's columns of the Jacobian are analytic: 1, x - W/2, y - H/2
+    __host__ __device__ static constexpr bool analytic(int k) { return k >= SKY; }
+    __device__ static float analytic_value(int k, float dx, float dy)
+    {
+        return k == SKY ? 1.0f : k == SKY + 1 ? dx : dy;
     }
     // d M / d u_DER at a pixel from the convolved light acc0 and planes acc
     __device__ static float derived(double acc0, const float *) { return kDMag * (float)acc0; }
     struct Prep {
         typename C::K k0;
-        double sky;
+        double sky, gx, gy;
     };
     __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw,
                                 int lane, Prep &p)
     {
         C::prep(u, cst, m0, H, W, osf, osw, lane, p.k0);
         p.sky = u[SKY];
+        p.gx = TILT ? u[SKY + 1] : 0.0;
+        p.gy = TILT ? u[SKY + 2] : 0.0;
+    }
+    // the unconvolved sky at a pixel at (dx, dy) from the cutout's centre
+    __device__ static double sky_at(const Prep &p, double dx, double dy)
+    {
+        if constexpr (TILT) return p.sky + p.gx * dx + p.gy * dy;
+        else return p.sky;
     }
     __device__ static const Geo &geo(const Prep &p, int) { return p.k0.g; }
     template <bool F64>
@@ -770,6 +790,7 @@ struct FamSingle {
     {
         C::guess(xc, yc, m, r0, q0, pa0, pk, NRAD, nat);
         nat[SKY] = sky0;
+        if (TILT) nat[SKY + 1] = nat[SKY + 2] = 0.0;
     }
     static constexpr int NCAN = 1;
     __host__ __device__ static void canon(int, int &iq, int &ith, int &is0, int &is1)
@@ -788,6 +809,8 @@ struct FamPair {
     static constexpr int ND = C1::NS > C2::NS ? C1::NS : C2::NS;
     static constexpr int DER = -1, NPL = P;
     __host__ __device__ static constexpr int plane(int k) { return k == SKY ? -1 : k + 1; }
+    __host__ __device__ static constexpr bool analytic(int k) { return k == SKY; }
+    __device__ static float analytic_value(int, float, float) { return 1.0f; }
     __device__ static float derived(double, const float *) { return 0.0f; }
     __host__ __device__ static constexpr int kind(int k)
     {
@@ -809,6 +832,7 @@ struct FamPair {
         C2::prep(u2, cst + 2, m0, H, W, osf, osw, lane, p.k1);
         p.sky = u[SKY];
     }
+    __device__ static double sky_at(const Prep &p, double, double) { return p.sky; }
     __device__ static const Geo &geo(const Prep &p, int c) { return c == 0 ? p.k0.g : p.k1.g; }
     template <bool F64>
     __device__ static void comp_pt(const Prep &p, int c, double dx, double dy, double &I, float *d)
@@ -852,6 +876,7 @@ struct FamPair {
 };
 
 using FamSersic = FamSingle<Sersic>;
+using FamSersicTilt = FamSingle<Sersic, true>;
 using FamBulgeDisk = FamPair<Sersic, ExpDisk>;
 using FamSersicBar = FamPair<Sersic, Ferrer>;
 

@@ -443,10 +443,12 @@ __device__ inline void tile_planes(const EvalShared<F> &sh, float *buf, int H, i
 }
 
 // d M / d u_k at output column t of this thread's strip.
+// (dx, dy): the pixel's offset from the cutout's centre (analytic sky columns).
 template <class F>
-__device__ inline float jac_at(int k, int t, const double (&acc0)[4], const float (&acc)[F::NPL][4])
+__device__ inline float jac_at(int k, int t, const double (&acc0)[4], const float (&acc)[F::NPL][4], float dx,
+                               float dy)
 {
-    if (k == F::SKY) return 1.0f;
+    if (F::analytic(k)) return F::analytic_value(k, dx, dy);
     if (k == F::DER) {
         float col[F::NPL];
 #pragma unroll
@@ -498,7 +500,6 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     const int H = me.h, W = me.w, K = me.k;
     const int tid = threadIdx.x;
     eval_prologue<F>(u, ma, H, W, sh, planes);
-    const double sky = sh.prep.sky;
     const cfloat *psf = (const cfloat *)(ba.psf + uniform64(me.psf_off));
     // Per-thread partial sums: chi^2 in FP64 (it decides accept/reject), g and
     // A in FP32 (a thread sums at most a few hundred pixels of them).
@@ -527,17 +528,19 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
                     float d;
                     const float wgt = pixel_weight(ba, idx, d) * bw[t];
                     if (wgt == 0.0f) continue;
-                    const double res = (double)d - (acc0[t] + sky);
+                    const double pdx = ((double)j + 0.5) - 0.5 * W, pdy = 0.5 * H - ((double)i + 0.5);
+                    const double res = (double)d - (acc0[t] + F::sky_at(sh.prep, pdx, pdy));
                     c2 = fma((double)wgt * res, res, c2);
                     const float wr = wgt * (float)res;
+                    const float fdx = (float)pdx, fdy = (float)pdy;
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
-                        const float Jk = jac_at<F>(k, t, acc0, acc);
+                        const float Jk = jac_at<F>(k, t, acc0, acc, fdx, fdy);
                         red[k] = fmaf(wr, Jk, red[k]);
                         const float wj = wgt * Jk;
 #pragma unroll
                         for (int l = 0; l <= k; ++l) {
-                            const float Jl = jac_at<F>(l, t, acc0, acc);
+                            const float Jl = jac_at<F>(l, t, acc0, acc, fdx, fdy);
                             red[P + k * (k + 1) / 2 + l] = fmaf(wj, Jl, red[P + k * (k + 1) / 2 + l]);
                         }
                     }
@@ -1303,20 +1306,22 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
                 const int j = tj0 + 4 * cg + t;
                 if (j >= W) continue;
                 const int64_t pix = (int64_t)i * W + j;
+                const double pdx = ((double)j + 0.5) - 0.5 * W, pdy = 0.5 * H - ((double)i + 0.5);
+                const float fdx = (float)pdx, fdy = (float)pdy;
                 if (ia.mode == 0) {
-                    ia.out[me.img_off + pix] = (float)(acc0[t] + esh.prep.sky);
+                    ia.out[me.img_off + pix] = (float)(acc0[t] + F::sky_at(esh.prep, pdx, pdy));
                 } else if (ia.mode == 1) {
                     float *jo = ia.out + (int64_t)ma.p * me.img_off;
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
                         if (!sfree[k]) continue;
-                        float jv = jac_at<F>(k, t, acc0, acc);
+                        float jv = jac_at<F>(k, t, acc0, acc, fdx, fdy);
                         jo[(int64_t)ma.col[k] * H * W + pix] = jv * (float)sdu[k];
                     }
                 } else {
                     const double gw = (double)ia.gin[me.img_off + pix];
 #pragma unroll
-                    for (int k = 0; k < P; ++k) v[k] += (double)jac_at<F>(k, t, acc0, acc) * gw;
+                    for (int k = 0; k < P; ++k) v[k] += (double)jac_at<F>(k, t, acc0, acc, fdx, fdy) * gw;
                 }
             }
         }

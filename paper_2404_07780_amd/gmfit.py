@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 
 GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_CONVERGED, ST_MAXITER, ST_STALLED, ST_NONFINITE = 0, 1, 2, 3
-SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
+SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 
 # exported symbols (one per declaration of include/gmfit.h)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",

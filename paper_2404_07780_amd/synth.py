@@ -44,7 +44,7 @@ M0 = 22.5
 READ_NOISE = 5.0
 
 # profile type codes shared by the C interfaces of both implementations
-SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY = range(1, 8)
+SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 
 # Model layouts: list of (type, convolve, idx per natural slot, fixed values).
 # Parameter vector of "sersic": x0 y0 mag re n q pa sky.
@@ -57,6 +57,15 @@ MODEL_SPECS: Dict[str, dict] = {
             (SKY, 0, [7], []),
         ],
         names=["x0", "y0", "mag", "re", "n", "q", "pa", "sky"],
+    ),
+    # single Sersic + the tilted-plane sky of Appendix D: ... sky kx ky
+    "sersic_tilt": dict(
+        p=10,
+        comps=[
+            (SERSIC, 1, [0, 1, 2, 3, 4, 5, 6], []),
+            (SKYPLANE, 0, [7, 8, 9], []),
+        ],
+        names=["x0", "y0", "mag", "re", "n", "q", "pa", "sky", "kx", "ky"],
     ),
     "bulgedisk": dict(
         p=12,
@@ -101,6 +110,7 @@ MODEL_SPECS: Dict[str, dict] = {
 # ("amp", col) scale by F
 FLUX_COLUMNS = {
     "sersic": [("mag", 2)],
+    "sersic_tilt": [("mag", 2)],
     "bulgedisk": [("mag", 2), ("mag", 7)],
     "sersicbar": [("mag", 2), ("mag", 7)],
     "king": [("amp", 2)],

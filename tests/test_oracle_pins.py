@@ -338,6 +338,7 @@ CASES = {
     "gaussian": (single(O.GAUSSIAN, sky=True), [10.55, 10.45, 30.0, 3.1, 0.7, 20.0, 1.0]),
     "moffat_point": (single(O.MOFFAT, convolve=False, fixed={"beta": 3.0}, sky=True),
                      [10.55, 10.45, 17.0, 2.5, 0.8, 50.0, 1.0]),
+    "sersic_tilt": (from_spec("sersic_tilt"), [10.52, 10.47, 18.0, 3.0, 1.5, 0.6, 30.0, 2.0, 0.03, -0.05]),
 }
 
 
@@ -462,3 +463,54 @@ def test_default_guess_border_sky_and_empty_image(orc):
     p, mom = orc.default_guess(single(O.SERSIC, sky=True), img, sig)
     assert p[7] == 7.25
     assert p[0] == 15.0 and p[1] == 15.0 and p[3] == 3.0 and p[5] == 1.0
+
+
+
+# ---------------------------------------------------------------- tilted-plane sky
+def test_plane_sky_is_the_appendix_plane(orc):
+    """Sersic + plane sky = Sersic alone + sky + kx (x - W/2) + ky (y - H/2)
+    on the pixel grid of Appendix C (x = j + 0.5, y = H - i - 0.5: y up)."""
+    H, W = 30, 36
+    psf = _psf()
+    m = from_spec("sersic_tilt")
+    p = [17.3, 14.6, 18.5, 3.2, 2.1, 0.7, 40.0, 5.0, 0.25, -0.4]
+    tot = orc.model_image(m, H, W, psf, p)
+    gal = orc.model_image(single(O.SERSIC), H, W, psf, p[:7])
+    x = np.arange(W) + 0.5
+    y = H - np.arange(H) - 0.5
+    plane = 5.0 + 0.25 * (x[None, :] - W / 2) - 0.4 * (y[:, None] - H / 2)
+    assert np.max(np.abs(tot - (gal + plane))) < 1e-12 * np.abs(tot).max()
+    # orientation: kx > 0 raises the right-hand columns, ky > 0 the top rows (small row index)
+    flat = orc.model_image(m, H, W, psf, p[:7] + [5.0, 0.0, 0.0])
+    right = orc.model_image(m, H, W, psf, p[:7] + [5.0, 0.1, 0.0])
+    up = orc.model_image(m, H, W, psf, p[:7] + [5.0, 0.0, 0.1])
+    assert (right - flat)[:, -1].min() > 0 and (right - flat)[:, 0].max() < 0
+    assert (up - flat)[0, :].min() > 0 and (up - flat)[-1, :].max() < 0
+
+
+def test_plane_sky_linear_subproblem_closed_form(orc):
+    # galaxy shape fixed, magnitude and the plane free: the model F U + s + kx dx
+    # + ky dy is linear, so the LM optimum and covariance are weighted least squares
+    shape = dict(x0=15.2, y0=16.7, re=3.5, n=1.8, q=0.7, pa=10.0)
+    gal = single(O.SERSIC, free={"mag"}, fixed=shape)
+    m = O.Model([gal.comps[0], O.Comp(O.SKYPLANE, False, [1, 2, 3], [])], 4)
+    H = W = 32
+    psf = _psf()
+    U = orc.model_image(single(O.SERSIC), H, W, psf, [15.2, 16.7, 22.5, 3.5, 1.8, 0.7, 10.0])
+    dx = (np.arange(W) + 0.5 - W / 2)[None, :] * np.ones((H, 1))
+    dy = (H - np.arange(H) - 0.5 - H / 2)[:, None] * np.ones((1, W))
+    rng = np.random.default_rng(3)
+    sig = rng.uniform(0.5, 2.0, (H, W))
+    d = (250.0 * U + 4.0 + 0.05 * dx - 0.03 * dy + sig * rng.normal(size=(H, W))).astype(np.float32)
+    sig = sig.astype(np.float32)
+    Wt = 1.0 / sig.astype(np.float64).ravel() ** 2
+    X = np.stack([U.ravel(), np.ones(H * W), dx.ravel(), dy.ravel()], 1)
+    A = X.T @ (Wt[:, None] * X)
+    sol = np.linalg.solve(A, X.T @ (Wt * d.astype(np.float64).ravel()))
+    p, chi2, nit, st = orc.fit(m, d, sig, psf, [22.5 - 2.5 * math.log10(100.0), 0.0, 0.0, 0.0], step_tol=1e-9)
+    assert st == O.ST_CONVERGED
+    F = 10 ** (-0.4 * (p[0] - 22.5))
+    assert abs(F / sol[0] - 1) < 1e-9 and np.allclose(p[1:], sol[1:], rtol=1e-8, atol=1e-10)
+    err = orc.param_errors(m, d, sig, psf, p)
+    cov = np.linalg.inv(A)
+    assert np.allclose(err[1:], np.sqrt(np.diag(cov))[1:], rtol=1e-6)

@@ -228,7 +228,7 @@ def bootstrap_baseline(n_sample: int, n_boot: int, seed: int, boot_seed: int, gm
             continue
         d = rp[sel][cv] - fit[g]
         d[:, ipa] = (d[:, ipa] + 90.0) % 180.0 - 90.0
-        ref = d.std(axis=0, ddof=1)
+        ref = d.std(axis=0, ddof=0)
         worst = max(worst, float(np.max(np.abs(gerr[g] - ref) / ref)))
     cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
                sample=f"galaxies 0..{n_sample - 1} of the workload (rendered and noised on the host), {n_boot} "

@@ -190,9 +190,10 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                     const double *params, double *err_out, double *cov_out, void *stream);
 
-/* Bootstrap errors.  Sec. 5.2 names the bootstrap as the alternative to the
- * covariance errors without fixing what is resampled; this library's reading
- * is the Poisson bootstrap of the pixels.  Replica r of galaxy g multiplies
+/* Bootstrap errors (Sec. 5.2: each galaxy image resampled with replacement,
+ * typically 100 times, and refitted; sigma^2 = (1/M) sum (m_i - mean)^2).
+ * The resampling of the pixels with replacement is taken in its limit for
+ * many pixels, independent Poisson(1) pixel weights (the Poisson bootstrap).  Replica r of galaxy g multiplies
  * every pixel weight Omega / sigma^2 by w ~ Poisson(1): w = the number of
  * thresholds T_k <= x, T_k = floor(2^32 F(k)) for k = 0..11 with
  * F(k) = e^-1 sum_{j<=k} 1/j! summed in that order in FP64, x the word
@@ -200,9 +201,10 @@ int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
  * word, seed high word) with counter {pixel / 4, g, r, 1} (pixel: row-major
  * index in the cutout).  Every replica is fitted by LM from params (device
  * [n_gal][p], normally the fit) with opts (opts->active and err_out are
- * ignored).  err_out (device [n_gal][p]): the sample standard deviation over
- * the replicas that end GM_ST_CONVERGED, position angles as differences from
- * params wrapped into (-90, 90]; NaN with fewer than two.  rep_params_out
+ * ignored).  err_out (device [n_gal][p]): sigma with sigma^2 = (1/M) sum
+ * (p_r - mean)^2 over the M replicas that end GM_ST_CONVERGED (Sec. 5.2),
+ * position angles as differences from params wrapped into (-90, 90]; NaN
+ * with fewer than two.  rep_params_out
  * (nullable, device [n_gal][n_boot][p]), rep_status_out and rep_niter_out
  * (nullable, device [n_gal][n_boot]) receive the replica fits.  2 <= n_boot, n_gal n_boot <=
  * 2^30; the replicas share the galaxies' pixels (nothing is copied). */

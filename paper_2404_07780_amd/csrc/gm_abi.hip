@@ -537,9 +537,10 @@ __global__ void replicate_kernel(const double *src, double *dst, int n_gal, int 
     dst[i] = src[(fit / nb) * p + k];
 }
 
-// Bootstrap standard deviation of column k of galaxy g over its replicas that
-// converged: sample standard deviation (two passes, replicas in order) of the
-// differences from params[g][k], wrapped into (-90, 90] for position angles.
+// Bootstrap error of column k of galaxy g over its m replicas that converged:
+// sigma^2 = (1/m) sum (p_r - mean)^2 (Sec. 5.2; two passes, replicas in order)
+// of the differences from params[g][k], wrapped into (-90, 90] for position
+// angles.
 __global__ void boot_reduce_kernel(int n_gal, int nb, int p, uint32_t pa_mask, const double *params,
                                    const double *rep, const int *status, double *err)
 {
@@ -576,7 +577,7 @@ __global__ void boot_reduce_kernel(int n_gal, int nb, int p, uint32_t pa_mask, c
             const double e = diff(r) - mean;
             ss += e * e;
         }
-    err[i] = sqrt(ss / (m - 1));
+    err[i] = sqrt(ss / m);
 }
 
 }  // namespace

@@ -33,7 +33,7 @@ def _boot_std(reps, ref, pa_cols):
         x = np.fmod(d[:, k], 180.0)
         x = np.where(x > 90.0, x - 180.0, x)
         d[:, k] = np.where(x <= -90.0, x + 180.0, x)
-    return d.std(axis=0, ddof=1)
+    return d.std(axis=0, ddof=0)          # sigma^2 = (1/M) sum (p - mean)^2, Sec. 5.2
 
 
 @pytest.mark.parametrize("cfg,n,nb", [("sersic64", 4, 6), ("uneven", 2, 6)])

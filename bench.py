@@ -85,6 +85,11 @@ WORKLOADS = {
     "paper": dict(n=8289, cfg="paper", seed=0,
                   desc="the shapes of the paper's SDSS test: 8289 single-Sersic galaxies, 128x128, one Moffat PSF "
                        "(beta 3, FWHM 3.03 px) on 41x41, Poisson + 5 e- read noise, LM from moment-based start"),
+    "adam": dict(n=8192, cfg="sersic64", seed=2,
+                 desc="the paper's fitter: gradient descent with Adam (1000 steps, rate 0.01 in the fit variables, "
+                      "betas 0.9/0.999) on 8192 held-out single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px "
+                      "on 15x15, unit-sigma noise, from the moment start; LM on the same batch and kernels as "
+                      "context"),
     "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
                       desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
                            "25x25, Poisson + read noise, LM from moment-based start"),
@@ -291,6 +296,116 @@ def bootstrap_main(args, n: int, seed: int):
     print(json.dumps(outj))
 
 
+ADAM = dict(steps=1000, lr=0.01, beta1=0.9, beta2=0.999)
+
+
+def adam_baseline(n_sample: int, seed: int, gm: G.Model):
+    """FP64 oracle Adam on galaxies 0..n_sample-1 (images rendered and noised
+    on the host) from its moment start, all host cores; the GPU's Adam of the
+    same data from the same start is compared with it.  After 1000 steps the
+    two trajectories circle the minimum apart, so the comparison is in units
+    of the fit's covariance error, and by chi^2."""
+    import oracle as O
+    from tests.gpu_helpers import oracle_batch
+    from tests.oracle_models import from_spec
+
+    ncores = len(os.sched_getaffinity(0))
+    b = oracle_batch("sersic64", n_sample, seed=seed)
+    om = from_spec(b.model)
+    ipa = S.MODEL_SPECS[b.model]["names"].index("pa")
+    ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma)
+    t0 = time.perf_counter()
+    rp, rc, rs = O.fit_adam_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
+                                  nthreads=ncores, **ADAM)
+    dt = time.perf_counter() - t0
+    db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf)
+    gp, gc, gs = [t.cpu().numpy() for t in G.gm_fit_adam(gm, db, ostart, **ADAM)]
+    worst = 0.0
+    for g in range(b.n):
+        err = O.param_errors(om, b.image(b.data, g), b.image(b.sigma, g), b.psf_of(g), rp[g])
+        d = gp[g] - rp[g]
+        d[ipa] = (d[ipa] + 90.0) % 180.0 - 90.0
+        worst = max(worst, float(np.max(np.abs(d) / err)))
+    cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
+               sample=f"galaxies 0..{n_sample - 1} of the workload (rendered and noised on the host), "
+                      f"{ADAM['steps']} Adam steps each, {dt:.1f} s")
+    parity = dict(sample=n_sample, status_equal=bool(np.array_equal(gs, rs)),
+                  worst_dp_over_sigma=worst, chi2_max_rel_diff=float(np.max(np.abs(gc / rc - 1))))
+    return cpu, parity
+
+
+def adam_main(args, n: int, seed: int):
+    """--workload adam: one step = moment start + gm_fit_adam of the batch.
+    The plain LM of the same batch, on the same kernels, runs after the timed
+    region as context (its throughput, and how close Adam's chi^2 comes)."""
+    from paper_2404_07780_amd import tune
+    from tests.gpu_helpers import param_parity
+
+    b, gm, db = make_batch("sersic64", n, seed)
+    tune.apply(gm, db, sample=n, trials=0)
+    ctx = G.context()
+    dev, p = db.device, gm.p
+    out = (torch.empty(n, p, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
+           torch.empty(n, dtype=torch.int32, device=dev))
+
+    def step(ev):
+        if ev:
+            ev[0].record()
+        guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
+        if ev:
+            ev[1].record()
+        G.gm_fit_adam(gm, db, guess, ctx=ctx, out=out, **ADAM)
+        if ev:
+            ev[2].record()
+
+    wall, evs = timed(step, args.steps, args.warmup, "adam")
+    ms = float(np.mean([evs[i][1].elapsed_time(evs[i][2]) for i in range(args.steps)]))
+    ap_, ac, ast = [t.cpu().numpy() for t in out]
+    # Adam's evaluation: npl planes convolved, chi^2 and the gradient reduced (no normal matrix)
+    f_conv, _ = flops_per_eval(b, p, p - 1)
+    f_red = 2.0 * b.h.astype(np.float64) * b.w * (p + 1)
+    flops = float(np.sum((f_conv + f_red) * (ADAM["steps"] + 1)))
+    achieved = flops / (ms / 1e3) / 1e12
+    # context: the LM on the same batch and start
+    guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    G.gm_fit_batch(gm, db, guess, ctx=ctx)
+    e0.record()
+    lp, lc, ln, ls = G.gm_fit_batch(gm, db, guess, ctx=ctx)
+    e1.record()
+    torch.cuda.synchronize()
+    lm_ms = e0.elapsed_time(e1)
+    lp, lc, ln, ls = [t.cpu().numpy() for t in (lp, lc, ln, ls)]
+    ok = ls == G.ST_CONVERGED
+    excess = (ac[ok] - lc[ok]) / lc[ok]
+    names = S.MODEL_SPECS[b.model]["names"]
+    near = np.mean([param_parity(names, ap_[g], lp[g])[0].all() for g in np.where(ok)[0]])
+    cpu = parity = None
+    if args.cpu_sample != 0:
+        ns = 32 if args.cpu_sample is None else args.cpu_sample
+        log(f"cpu baseline: oracle Adam of {ns} galaxies")
+        cpu, parity = adam_baseline(ns, seed, gm)
+    outj = {
+        "metric": "galaxies fitted/s (gradient descent, Adam, 1000 steps)",
+        "value": n / (wall / args.steps), "unit": "galaxies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"adam: {WORKLOADS['adam']['desc']}", "n_gal": n, "seed": seed, **ADAM},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "adam_fit_kernel",
+                     "kernel_ms": ms, "flops_per_step": flops},
+        "vs_lm": {"lm_galaxies_per_s": n / (lm_ms / 1e3), "lm_mean_trials": float(ln.mean()),
+                  "lm_converged": float(ok.mean()), "adam_steps_per_s": n * ADAM["steps"] / (ms / 1e3),
+                  "lm_speedup": (ms / lm_ms),
+                  "adam_chi2_excess_over_lm_median": float(np.median(excess)),
+                  "adam_within_1e6_of_lm_chi2": float(np.mean(excess < 1e-6)),
+                  "adam_params_within_1e4_of_lm": float(near)},
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(outj))
+
+
 def timed(step, steps: int, warmup: int, name: str):
     for i in range(warmup):
         step(None)
@@ -397,6 +512,8 @@ def main():
     seed = wl["seed"] if args.seed is None else args.seed
     if args.workload == "bootstrap":
         return bootstrap_main(args, n, seed)
+    if args.workload == "adam":
+        return adam_main(args, n, seed)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
         args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32}.get(args.workload, 160)

@@ -190,6 +190,22 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
 int gm_param_errors(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                     const double *params, double *err_out, double *cov_out, void *stream);
 
+/* The paper's own fitter (Sec. 5.1: gradient descent; Adam in its examples)
+ * on the same model evaluation: Adam (Kingma and Ba 2015) on chi^2 in the LM
+ * variables (ln of scales and of n, radians for PA), gradient -2 J^T W r,
+ * `steps` steps of rate lr with bias-corrected moments (beta1, beta2, eps),
+ * the iterate clamped to the LM bounds after each step, fixed slots
+ * untouched; no convergence test.  params_inout as for gm_fit_batch
+ * (canonical form on return); chi2_out: chi^2 at the final parameters;
+ * status_out: GM_ST_MAXITER (all steps taken) or GM_ST_NONFINITE. */
+typedef struct {
+    int32_t steps;            /* Adam steps per galaxy (the paper's examples: 1000) */
+    double lr, beta1, beta2, eps;
+} gm_adam_opts;
+
+int gm_fit_adam(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_adam_opts *opts,
+                double *params_inout, double *chi2_out, int32_t *status_out, void *stream);
+
 /* Bootstrap errors (Sec. 5.2: each galaxy image resampled with replacement,
  * typically 100 times, and refitted; sigma^2 = (1/M) sum (m_i - mean)^2).
  * The resampling of the pixels with replacement is taken in its limit for

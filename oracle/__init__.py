@@ -75,6 +75,11 @@ class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("lambda0", C.c_double), ("step_tol", C.c_double)]
 
 
+class _AdamOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
+
+
 @dataclass
 class Comp:
     type: int
@@ -137,6 +142,8 @@ def lib():
         L.orc_moments.argtypes = [i, i, p, p, p, d, p]
         L.orc_moments.restype = None
         L.orc_fit_batch.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p, p, p, p, i]
+        L.orc_fit_adam.argtypes = [p, i, i, p, p, p, p, i, p, p, p, p]
+        L.orc_fit_adam_batch.argtypes = [p, i, p, p, p, p, p, p, p, p, p, p, p, p, p, i]
         _lib = L
     return _lib
 
@@ -245,6 +252,26 @@ def fit(model: Model, data, sigma, psf, params0, omega=None, max_iter=100, lambd
     return params, chi2.value, nit.value, st.value
 
 
+def fit_adam(model: Model, data, sigma, psf, params0, omega=None, steps=1000, lr=0.01, beta1=0.9,
+             beta2=0.999, eps=1e-8):
+    """Gradient descent with Adam on chi^2 (Sec. 5.1), one galaxy; returns
+    (params, chi2, status)."""
+    data = _f32(data)
+    sigma = _f32(sigma)
+    psf = _f32(psf)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.uint8)
+    params = _f64(params0).copy()
+    chi2 = C.c_double()
+    st = C.c_int()
+    o = _AdamOpts(steps, lr, beta1, beta2, eps)
+    mc = model.c()
+    rc = lib().orc_fit_adam(C.byref(mc), data.shape[0], data.shape[1], _ptr(data), _ptr(sigma), _ptr(om),
+                            _ptr(psf), psf.shape[0], C.byref(o), _ptr(params), C.byref(chi2), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_fit_adam failed ({rc})")
+    return params, chi2.value, st.value
+
+
 def param_errors(model: Model, data, sigma, psf, params, omega=None, want_cov=False):
     data = _f32(data)
     sigma = _f32(sigma)
@@ -324,3 +351,32 @@ def fit_batch(model: Model, h, w, img_off, data, sigma, psf_k, psf_off, psf, par
                         _ptr(psf_k), _ptr(psf_off), _ptr(psf), C.byref(o), _ptr(params), _ptr(chi2),
                         _ptr(nit), _ptr(st), int(nthreads))
     return params, chi2, nit, st
+
+
+def fit_adam_batch(model: Model, h, w, img_off, data, sigma, psf_k, psf_off, psf, params0, omega=None,
+                   steps=1000, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, nthreads=None):
+    """Adam fits of a ragged batch on `nthreads` host threads; returns
+    (params, chi2, status)."""
+    h = np.ascontiguousarray(h, np.int32)
+    w = np.ascontiguousarray(w, np.int32)
+    img_off = np.ascontiguousarray(img_off, np.int64)
+    psf_k = np.ascontiguousarray(psf_k, np.int32)
+    psf_off = np.ascontiguousarray(psf_off, np.int64)
+    data = _f32(data)
+    sigma = _f32(sigma)
+    psf = _f32(psf)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.uint8)
+    n = len(h)
+    params = _f64(params0).reshape(n, model.p).copy()
+    chi2 = np.zeros(n)
+    st = np.zeros(n, np.int32)
+    o = _AdamOpts(steps, lr, beta1, beta2, eps)
+    if nthreads is None:
+        nthreads = len(os.sched_getaffinity(0))
+    mc = model.c()
+    rc = lib().orc_fit_adam_batch(C.byref(mc), n, _ptr(h), _ptr(w), _ptr(img_off), _ptr(data), _ptr(sigma),
+                                  _ptr(om), _ptr(psf_k), _ptr(psf_off), _ptr(psf), C.byref(o), _ptr(params),
+                                  _ptr(chi2), _ptr(st), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_fit_adam_batch failed ({rc})")
+    return params, chi2, st

@@ -943,6 +943,64 @@ done:
     return ORC_OK;
 }
 
+/* Gradient descent with Adam, the paper's own fitter (Sec. 5.1: gradient
+ * descent through pytorch's adaptive optimisers; its examples run 1000
+ * iterations).  The loss is chi^2 (Sec. 5.1) and the variables are the LM
+ * variables u (ln of scales and n, PA in radians, the rest as given), so the
+ * gradient is d chi^2/du = -2 J^T W r.  Adam's update (Kingma and Ba 2015,
+ * Algorithm 1): m <- b1 m + (1-b1) grad, v <- b2 v + (1-b2) grad^2,
+ * u <- u - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), then the LM bounds.
+ * All `steps` steps are taken (no convergence test); chi^2 is evaluated once
+ * more at the final u; the result is put in canonical form.  Status MAXITER,
+ * or NONFINITE as soon as chi^2 is not finite (u is then the last finite
+ * iterate's successor, as taken). */
+int orc_fit_adam(const orc_model *m, int h, int w, const float *data, const float *sigma,
+                 const uint8_t *omega, const float *psf, int k, const orc_adam_opts *o,
+                 double *params, double *chi2_out, int *status_out)
+{
+    if (orc_validate(m) || h < 1 || w < 1 || k < 1 || (k & 1) == 0 || !o || o->steps < 0)
+        return ORC_EINVAL;
+    int p = m->p, npix = h * w;
+    fit_ctx fc = {m, h, w, k, data, sigma, omega, NULL, NULL, NULL};
+    fc.psf = psf_to_double(psf, k);
+    fc.model = malloc(sizeof(double) * npix);
+    fc.jac = malloc(sizeof(double) * (size_t)p * npix);
+    if (!fc.psf || !fc.model || !fc.jac) {
+        free((void *)fc.psf); free(fc.model); free(fc.jac);
+        return ORC_ENOMEM;
+    }
+    double u[ORC_MAX_P], pt[ORC_MAX_P], g[ORC_MAX_P], A[ORC_MAX_P * ORC_MAX_P];
+    double m1[ORC_MAX_P] = {0}, m2[ORC_MAX_P] = {0};
+    for (int a = 0; a < p; ++a) u[a] = to_u(column_kind(m, a), params[a]);
+    clamp_u(m, h, w, u);
+    double chi2 = 0.0;
+    int status = ORC_ST_MAXITER;
+    for (int t = 1; t <= o->steps; ++t) {
+        u_to_params(m, u, pt);
+        normal_equations(&fc, pt, &chi2, g, A);
+        if (!isfinite(chi2)) { status = ORC_ST_NONFINITE; break; }
+        double c1 = 1.0 - pow(o->beta1, t), c2 = 1.0 - pow(o->beta2, t);
+        for (int a = 0; a < p; ++a) {
+            double grad = -2.0 * g[a];
+            m1[a] = o->beta1 * m1[a] + (1.0 - o->beta1) * grad;
+            m2[a] = o->beta2 * m2[a] + (1.0 - o->beta2) * grad * grad;
+            u[a] -= o->lr * (m1[a] / c1) / (sqrt(m2[a] / c2) + o->eps);
+        }
+        clamp_u(m, h, w, u);
+    }
+    if (status == ORC_ST_MAXITER) {
+        u_to_params(m, u, pt);
+        normal_equations(&fc, pt, &chi2, g, A);
+        if (!isfinite(chi2)) status = ORC_ST_NONFINITE;
+    }
+    u_to_params(m, u, params);
+    orc_canonicalise(m, params);
+    if (chi2_out) *chi2_out = chi2;
+    if (status_out) *status_out = status;
+    free((void *)fc.psf); free(fc.model); free(fc.jac);
+    return ORC_OK;
+}
+
 /* sigma_p = sqrt(diag (J^T W J)^-1) in natural units (Sec. 5.2), unscaled,
  * at the given parameters; cov (nullable) is the full natural-unit
  * covariance.  Returns ORC_ESINGULAR (errors NaN) if J^T W J is not PD. */
@@ -1156,6 +1214,7 @@ typedef struct {
     double *params, *chi2;
     int32_t *niter, *status;
     volatile long next;
+    const orc_adam_opts *adam;   /* non-NULL: Adam instead of LM */
 } batch_job;
 
 static void *batch_worker(void *arg)
@@ -1167,14 +1226,34 @@ static void *batch_worker(void *arg)
         int64_t off = b->img_off[gi];
         int nit = 0, st = 0;
         double c2 = 0.0;
-        orc_fit(b->m, b->h[gi], b->w[gi], b->data + off, b->sigma + off,
-                b->omega ? b->omega + off : NULL, b->psf + b->psf_off[gi], b->psf_k[gi], b->o,
-                b->params + (size_t)gi * b->m->p, &c2, &nit, &st);
+        if (b->adam) {
+            orc_fit_adam(b->m, b->h[gi], b->w[gi], b->data + off, b->sigma + off,
+                         b->omega ? b->omega + off : NULL, b->psf + b->psf_off[gi], b->psf_k[gi], b->adam,
+                         b->params + (size_t)gi * b->m->p, &c2, &st);
+        } else {
+            orc_fit(b->m, b->h[gi], b->w[gi], b->data + off, b->sigma + off,
+                    b->omega ? b->omega + off : NULL, b->psf + b->psf_off[gi], b->psf_k[gi], b->o,
+                    b->params + (size_t)gi * b->m->p, &c2, &nit, &st);
+            b->niter[gi] = nit;
+        }
         b->chi2[gi] = c2;
-        b->niter[gi] = nit;
         b->status[gi] = st;
     }
     return NULL;
+}
+
+static int run_batch(batch_job *job, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int i = 0; i < nthreads; ++i)
+        if (pthread_create(&th[i], NULL, batch_worker, job) == 0) started++;
+        else break;
+    if (started == 0) batch_worker(job);
+    for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
+    return ORC_OK;
 }
 
 int orc_fit_batch(const orc_model *m, int n_gal, const int32_t *h, const int32_t *w,
@@ -1185,15 +1264,19 @@ int orc_fit_batch(const orc_model *m, int n_gal, const int32_t *h, const int32_t
 {
     if (orc_validate(m)) return ORC_EINVAL;
     batch_job job = {m, n_gal, h, w, img_off, data, sigma, omega, psf_k, psf_off, psf, o,
-                     params, chi2, niter, status, 0};
-    if (nthreads < 1) nthreads = 1;
-    if (nthreads > 256) nthreads = 256;
-    pthread_t th[256];
-    int started = 0;
-    for (int i = 0; i < nthreads; ++i)
-        if (pthread_create(&th[i], NULL, batch_worker, &job) == 0) started++;
-        else break;
-    if (started == 0) batch_worker(&job);
-    for (int i = 0; i < started; ++i) pthread_join(th[i], NULL);
-    return ORC_OK;
+                     params, chi2, niter, status, 0, NULL};
+    return run_batch(&job, nthreads);
 }
+
+int orc_fit_adam_batch(const orc_model *m, int n_gal, const int32_t *h, const int32_t *w,
+                       const int64_t *img_off, const float *data, const float *sigma,
+                       const uint8_t *omega, const int32_t *psf_k, const int64_t *psf_off,
+                       const float *psf, const orc_adam_opts *o, double *params, double *chi2,
+                       int32_t *status, int nthreads)
+{
+    if (orc_validate(m) || !o || o->steps < 0) return ORC_EINVAL;
+    batch_job job = {m, n_gal, h, w, img_off, data, sigma, omega, psf_k, psf_off, psf, NULL,
+                     params, chi2, NULL, status, 0, o};
+    return run_batch(&job, nthreads);
+}
+

@@ -49,6 +49,12 @@ typedef struct {
     double lambda0, step_tol;
 } orc_lm_opts;
 
+/* Adam (Kingma and Ba 2015) on chi^2: steps, learning rate, moment decays, eps. */
+typedef struct {
+    int32_t steps;
+    double lr, beta1, beta2, eps;
+} orc_adam_opts;
+
 double orc_digamma(double x);
 double orc_gammainc_p(double a, double x);
 double orc_dgammainc_p_da(double a, double x);
@@ -67,6 +73,14 @@ int orc_jacobian(const orc_model *m, int h, int w, const float *psf, int k,
 int orc_fit(const orc_model *m, int h, int w, const float *data, const float *sigma,
             const uint8_t *omega, const float *psf, int k, const orc_lm_opts *o,
             double *params, double *chi2, int *niter, int *status);
+int orc_fit_adam(const orc_model *m, int h, int w, const float *data, const float *sigma,
+                 const uint8_t *omega, const float *psf, int k, const orc_adam_opts *o,
+                 double *params, double *chi2, int *status);
+int orc_fit_adam_batch(const orc_model *m, int n_gal, const int32_t *h, const int32_t *w,
+                       const int64_t *img_off, const float *data, const float *sigma,
+                       const uint8_t *omega, const int32_t *psf_k, const int64_t *psf_off,
+                       const float *psf, const orc_adam_opts *o, double *params, double *chi2,
+                       int32_t *status, int nthreads);
 int orc_param_errors(const orc_model *m, int h, int w, const float *data, const float *sigma,
                      const uint8_t *omega, const float *psf, int k, const double *params,
                      double *err, double *cov);

@@ -737,6 +737,23 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, nullptr, (hipStream_t)stream);
 }
 
+int gm_fit_adam(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_adam_opts *opts,
+                double *params_inout, double *chi2_out, int32_t *status_out, void *stream)
+{
+    Match mt;
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if (!opts || opts->steps < 0 || !(opts->lr > 0.0) || !(opts->beta1 >= 0.0 && opts->beta1 < 1.0) ||
+        !(opts->beta2 >= 0.0 && opts->beta2 < 1.0) || !(opts->eps > 0.0))
+        return GM_EINVAL;
+    if (batch->n_gal == 0) return GM_OK;
+    if (!params_inout || !chi2_out || !status_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    return v->adam(ctx, mt.ci, opts, params_inout, chi2_out, status_out, (hipStream_t)stream);
+}
+
 int gm_bootstrap(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
                  const double *params, int32_t n_boot, uint64_t seed, double *err_out, double *rep_params_out,
                  int32_t *rep_status_out, int32_t *rep_niter_out, void *stream)

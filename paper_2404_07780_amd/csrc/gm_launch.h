@@ -157,6 +157,20 @@ int launch_fit(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArg
 }
 
 template <class F, int NG, int KT>
+int launch_adam(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const AdamArgs &aa, size_t lds, int wpc,
+                hipStream_t st)
+{
+    auto kern = adam_fit_kernel<F, KT, NG>;
+    int per_cu;
+    int rc = prepare(kern, lds, &per_cu);
+    if (rc) return rc;
+    if (wpc > 0) per_cu = std::min(per_cu, wpc);
+    int grid = std::min(aa.n_gal, per_cu * c->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, aa);
+    return hip_rc(hipGetLastError());
+}
+
+template <class F, int NG, int KT>
 int launch_err(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, int wpc,
                hipStream_t st)
 {
@@ -188,6 +202,7 @@ struct Dispatch;
 template <class F, int NG>
 struct Dispatch<F, NG> {
     template <class... A> static int fit(int, A &&...a) { return launch_fit<F, NG, 0>(a...); }
+    template <class... A> static int adam(int, A &&...a) { return launch_adam<F, NG, 0>(a...); }
     template <class... A> static int err(int, A &&...a) { return launch_err<F, NG, 0>(a...); }
     template <class... A> static int img(int, A &&...a) { return launch_img<F, NG, 0>(a...); }
 };
@@ -196,6 +211,10 @@ struct Dispatch<F, NG, K0, KR...> {
     template <class... A> static int fit(int kt, A &&...a)
     {
         return kt == K0 ? launch_fit<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::fit(kt, a...);
+    }
+    template <class... A> static int adam(int kt, A &&...a)
+    {
+        return kt == K0 ? launch_adam<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::adam(kt, a...);
     }
     template <class... A> static int err(int kt, A &&...a)
     {
@@ -262,6 +281,42 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
         fa.boot_k1 = (uint32_t)(ex->boot_seed >> 32);
     }
     return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
+}
+
+template <class F, int NG, int... KTS>
+int run_adam(gm_ctx *c, const CallInfo &ci, const gm_adam_opts *o, double *params, double *chi2, int32_t *status,
+             hipStream_t st)
+{
+    const gm_batch *b = ci.b;
+    size_t lds;
+    int rc = check_lds<F, NG>(max_k(ci), &lds);
+    if (rc) return rc;
+    std::vector<int> order(b->n_gal);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(b->n_gal);
+    for (int g = 0; g < b->n_gal; ++g) {
+        double k = ci.convolved ? b->psf_k[g] : 1.0;
+        cost[g] = (double)b->h[g] * b->w[g] * k * k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    Staged sg;
+    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)b->n_gal, st, &sg);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
+    if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    AdamArgs aa{};
+    aa.order = reinterpret_cast<const int *>(sg.extra);
+    aa.n_gal = b->n_gal;
+    aa.queue = sg.queue;
+    aa.params = params;
+    aa.chi2 = chi2;
+    aa.status = status;
+    aa.steps = o->steps;
+    aa.lr = o->lr;
+    aa.beta1 = o->beta1;
+    aa.beta2 = o->beta2;
+    aa.eps = o->eps;
+    return Dispatch<F, NG, KTS...>::adam(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), aa, lds, ci.wpc, st);
 }
 
 template <class F, int NG, int... KTS>
@@ -359,6 +414,8 @@ struct Variant {
     int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t) = nullptr;
     int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t) = nullptr;
     int (*vjp)(gm_ctx *, const CallInfo &, const double *, const float *, double *, hipStream_t) = nullptr;
+    int (*adam)(gm_ctx *, const CallInfo &, const gm_adam_opts *, double *, double *, int32_t *,
+                hipStream_t) = nullptr;
 };
 
 template <class F, int NG, int... KTS>
@@ -372,6 +429,7 @@ Variant make_variant()
     v.image = run_image<F, NG, KTS...>;
     v.guess = run_guess<F>;
     v.vjp = run_vjp<F, NG, KTS...>;
+    v.adam = run_adam<F, NG, KTS...>;
     return v;
 }
 

@@ -29,7 +29,7 @@ SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_j
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise",
            "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch", "gm_plan_elapsed", "gm_plan_destroy",
-           "gm_bootstrap")
+           "gm_bootstrap", "gm_fit_adam")
 
 
 class GmError(RuntimeError):
@@ -52,6 +52,11 @@ class gm_batch(C.Structure):
     _fields_ = [("n_gal", C.c_int32), ("h", C.c_void_p), ("w", C.c_void_p), ("img_off", C.c_void_p),
                 ("psf_k", C.c_void_p), ("psf_off", C.c_void_p), ("data", C.c_void_p), ("sigma", C.c_void_p),
                 ("omega", C.c_void_p), ("psf", C.c_void_p)]
+
+
+class gm_adam_opts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
 
 
 class gm_fit_opts(C.Structure):
@@ -117,13 +122,14 @@ def lib() -> C.CDLL:
         L.gm_plan_launch.argtypes = [v, v]
         L.gm_bootstrap.argtypes = [v, p, p, p, v, i, u64, v, v, v, v, v]
         L.gm_plan_elapsed.argtypes = [v, v]
+        L.gm_fit_adam.argtypes = [v, p, p, p, v, v, v, v]
         L.gm_plan_destroy.argtypes = [v]
         L.gm_plan_destroy.restype = None
         for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise", "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch",
-                     "gm_plan_elapsed", "gm_bootstrap"):
+                     "gm_plan_elapsed", "gm_bootstrap", "gm_fit_adam"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -368,6 +374,28 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
     return params, chi2, niter, status
+
+
+def gm_fit_adam(model: Model, batch: Batch, params0, steps: int = 1000, lr: float = 0.01, beta1: float = 0.9,
+                beta2: float = 0.999, eps: float = 1e-8, ctx: Optional[Context] = None, out=None):
+    """Gradient descent with Adam on chi^2 (the paper's fitter, Sec. 5.1).
+    Returns (params, chi2, status) as device tensors; `out` may pass
+    preallocated (params, chi2, status), params then overwritten with params0
+    first unless params0 is None."""
+    ctx = ctx or context(batch.device.index)
+    if out is None:
+        params = _params_dev(params0, batch, model.p).clone()
+        chi2 = torch.empty(batch.n, dtype=torch.float64, device=batch.device)
+        status = torch.empty(batch.n, dtype=torch.int32, device=batch.device)
+    else:
+        params, chi2, status = out
+        if params0 is not None:
+            params.copy_(_params_dev(params0, batch, model.p))
+    o = gm_adam_opts(int(steps), float(lr), float(beta1), float(beta2), float(eps))
+    m, b = model.c(), batch.c()
+    _check("gm_fit_adam", lib().gm_fit_adam(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
+                                            _ptr(chi2), _ptr(status), _stream()))
+    return params, chi2, status
 
 
 def gm_bootstrap(model: Model, batch: Batch, params, n_boot: int = 100, seed: int = 0, max_iter: int = 100,

@@ -29,7 +29,7 @@ MAX_COMP, MAX_SLOTS, MAX_P = 4, 8, 16
 
 # natural slots of each profile type
 SLOTS = {
-    SERSIC: ("x0", "y0", "mag", "re", "n", "q", "pa"),
+    SERSIC: ("x0", "y0", "mag", "re", "n", "q", "pa", "box"),
     EXPDISK: ("x0", "y0", "mag", "rs", "q", "pa"),
     FERRER: ("x0", "y0", "mag", "rout", "q", "pa", "a", "b"),
     KING: ("x0", "y0", "I0", "rc", "rt", "q", "pa", "alpha"),

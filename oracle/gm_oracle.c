@@ -174,11 +174,11 @@ double orc_sersic_db(double n)
  * natural log for every positive scale and for the Sersic index; radians for
  * the position angle (the paper's `log=True` / `angle=True` flags,
  * Appendix A, extended to the other scales). */
-enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE, K_SKYGRAD };
+enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE, K_SKYGRAD, K_BOX };
 
 static const int slot_kind[9][ORC_MAX_SLOTS] = {
     /* 0 unused */ {0},
-    /* SERSIC   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_N, K_Q, K_PA, K_NONE},
+    /* SERSIC   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_N, K_Q, K_PA, K_BOX},
     /* EXPDISK  */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_NONE, K_NONE},
     /* FERRER   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_SHAPE, K_SHAPE},
     /* KING     */ {K_X0, K_Y0, K_AMP, K_SCALE, K_SCALE, K_Q, K_PA, K_SHAPE},
@@ -285,6 +285,7 @@ typedef struct {
     double scale, scale2, a_f, b_f, alpha, beta, rd;
     double kA, dkA_dlnrc, dkA_dlnrt;   /* King: T^(-1/alpha) and derivatives */
     double xc, yc;               /* plane sky: the cutout's geometric centre */
+    double cbox, dlrbox;         /* Sersic: exponent c = B + 2 of eq. (r), d ln r_box / dc */
 } comp_prep;
 
 static void prep_component(const orc_model *m, int c, const double *params, comp_prep *cp)
@@ -305,12 +306,18 @@ static void prep_component(const orc_model *m, int c, const double *params, comp
     double lnF = -0.4 * ORC_LN10 * (v[2] - m->m0);  /* ln 10^(-0.4(m-m0)) */
     switch (cp->type) {
     case ORC_SERSIC: {
-        double re = v[3], n = v[4];
+        double re = v[3], n = v[4], c = v[7] + 2.0;
         cp->re = re; cp->n = n;
         cp->b = orc_sersic_b(n);
         cp->db = orc_sersic_db(n);
-        /* I_e = F b^(2n) / (2 pi q re^2 n Gamma(2n) e^b) */
-        cp->lnamp = lnF + 2.0 * n * log(cp->b) - log(2.0 * ORC_PI * q * re * re * n) - lgamma(2.0 * n) - cp->b;
+        /* eq. (rbox): r_box = pi c / (2 beta(1/c, 1/c)), c = B + 2, beta(a, a) =
+         * Gamma(a)^2 / Gamma(2a); d ln r_box / dc = 1/c + 2 (psi(1/c) - psi(2/c)) / c^2 */
+        double lnrbox = log(ORC_PI * c / 2.0) - (2.0 * lgamma(1.0 / c) - lgamma(2.0 / c));
+        cp->cbox = c;
+        cp->dlrbox = 1.0 / c + 2.0 * (orc_digamma(1.0 / c) - orc_digamma(2.0 / c)) / (c * c);
+        /* eq. (sersicLtot): I_e = r_box F b^(2n) / (2 pi q re^2 n Gamma(2n) e^b) */
+        cp->lnamp = lnF + lnrbox + 2.0 * n * log(cp->b) - log(2.0 * ORC_PI * q * re * re * n) - lgamma(2.0 * n)
+                    - cp->b;
         break;
     }
     case ORC_EXPDISK: {
@@ -370,20 +377,41 @@ static void comp_point(const comp_prep *cp, double x, double y, double *I, doubl
         dI[2] = y - cp->yc;
         return;
     }
-    /* rotate into the component frame (Sec. 4.1, B = 0) */
+    /* rotate into the component frame (Sec. 4.1) */
     double dx = x - cp->v[0], dy = y - cp->v[1];
     double X = cp->cth * dx + cp->sth * dy;
     double Y = -cp->sth * dx + cp->cth * dy;
     double q = cp->q;
-    double r2raw = X * X + Y * Y / (q * q);
-    double r2 = r2raw, floored = 0.0;
-    if (r2 < 1e-12) { r2 = 1e-12; floored = 1.0; }
-    /* d r^2 / d(x0, y0, theta, q); zero where the cusp floor is active */
-    double g = 1.0 - floored;
-    double dr2_dx0 = g * (-2.0 * X * cp->cth + 2.0 * Y * cp->sth / (q * q));
-    double dr2_dy0 = g * (-2.0 * X * cp->sth - 2.0 * Y * cp->cth / (q * q));
-    double dr2_dth = g * (2.0 * X * Y * (1.0 - 1.0 / (q * q)));
-    double dr2_dq  = g * (-2.0 * Y * Y / (q * q * q));
+    double r2, floored = 0.0, dr2_dx0, dr2_dy0, dr2_dth, dr2_dq, dr2_dc = 0.0;
+    if (cp->type == ORC_SERSIC) {
+        /* eq. (r) with boxiness: r = (|X|^c + |Y/q|^c)^(1/c), c = B + 2 */
+        double c = cp->cbox, ax = fabs(X), ay = fabs(Y) / q;
+        double A = pow(ax, c), Bq = pow(ay, c), S = A + Bq;
+        r2 = pow(S, 2.0 / c);
+        if (r2 < 1e-12) {
+            r2 = 1e-12; floored = 1.0;
+            dr2_dx0 = dr2_dy0 = dr2_dth = dr2_dq = 0.0;
+        } else {
+            /* d ln r / dX = A / (S X), d ln r / dY = Bq / (S Y) (0 on the axes, c > 1) */
+            double lx = X != 0.0 ? A / (S * X) : 0.0, ly = Y != 0.0 ? Bq / (S * Y) : 0.0;
+            dr2_dx0 = 2.0 * r2 * (-cp->cth * lx + cp->sth * ly);
+            dr2_dy0 = 2.0 * r2 * (-cp->sth * lx - cp->cth * ly);
+            dr2_dth = 2.0 * r2 * (Y * lx - X * ly);
+            dr2_dq = 2.0 * r2 * (-Bq / (q * S));
+            double tA = ax > 0.0 ? A * log(ax) : 0.0, tB = ay > 0.0 ? Bq * log(ay) : 0.0;
+            dr2_dc = 2.0 * r2 * (-log(S) / (c * c) + (tA + tB) / (c * S));
+        }
+    } else {
+        double r2raw = X * X + Y * Y / (q * q);
+        r2 = r2raw;
+        if (r2 < 1e-12) { r2 = 1e-12; floored = 1.0; }
+        /* d r^2 / d(x0, y0, theta, q); zero where the cusp floor is active */
+        double g = 1.0 - floored;
+        dr2_dx0 = g * (-2.0 * X * cp->cth + 2.0 * Y * cp->sth / (q * q));
+        dr2_dy0 = g * (-2.0 * X * cp->sth - 2.0 * Y * cp->cth / (q * q));
+        dr2_dth = g * (2.0 * X * Y * (1.0 - 1.0 / (q * q)));
+        dr2_dq  = g * (-2.0 * Y * Y / (q * q * q));
+    }
 
     double val = 0.0, dl_dr2 = 0.0, dl_dq_direct = 0.0;
     int sq = 4, spa = 5;    /* slots of q and PA */
@@ -403,6 +431,7 @@ static void comp_point(const comp_prep *cp, double x, double y, double *I, doubl
                      - 2.0 * orc_digamma(2.0 * n) - db * z
                      + b * z * L / (2.0 * n * n);
         dI[4] = val * n * dl_dn;                                 /* ln n */
+        dI[7] = val * (cp->dlrbox + dl_dr2 * dr2_dc);            /* B */
         break;
     }
     case ORC_EXPDISK: {
@@ -756,7 +785,8 @@ static void chol_inverse(int p, const double *L, double *inv)
 /* Bounds of the LM variables, applied after every trial step (natural units
  * converted to u): centres inside the cutout, positive scales in
  * [0.1, 2 max(H, W)] px, Sersic index in [0.2, 10], axis ratio in
- * [0.05, 20] (q > 1 is allowed during the fit and canonicalised at the end). */
+ * [0.05, 20] (q > 1 is allowed during the fit and canonicalised at the end),
+ * boxiness B in [-0.9, 2] (c = B + 2 in [1.1, 4]). */
 static void clamp_u(const orc_model *m, int h, int w, double *u)
 {
     double big = 2.0 * (h > w ? h : w);
@@ -769,6 +799,7 @@ static void clamp_u(const orc_model *m, int h, int w, double *u)
         case K_SCALE: lo = log(0.1); hi = log(big); break;
         case K_N: lo = log(0.2); hi = log(10.0); break;
         case K_Q: lo = 0.05; hi = 20.0; break;
+        case K_BOX: lo = -0.9; hi = 2.0; break;
         default: break;
         }
         if (u[k] < lo) u[k] = lo;

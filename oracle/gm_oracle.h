@@ -16,7 +16,7 @@ enum { ORC_SERSIC = 1, ORC_EXPDISK, ORC_FERRER, ORC_KING, ORC_GAUSSIAN, ORC_MOFF
 enum { ORC_ST_CONVERGED = 0, ORC_ST_MAXITER = 1, ORC_ST_STALLED = 2, ORC_ST_NONFINITE = 3 };
 
 /* One component.  Natural slots per type (PA in degrees):
- *   SERSIC   x0 y0 mag r_e n q pa
+ *   SERSIC   x0 y0 mag r_e n q pa box    (box: B of eq. (r); 0 = ellipse)
  *   EXPDISK  x0 y0 mag r_s q pa
  *   FERRER   x0 y0 mag r_out q pa a b          (a, b always fixed)
  *   KING     x0 y0 I0 r_c r_t q pa alpha       (alpha always fixed)

@@ -53,7 +53,12 @@ enum {
 };
 
 /* Profile types (Sec. 4): natural parameter slots of each, in order
- *   GM_SERSIC   x0 y0 mag r_e n q pa        Sec. 4.1, eqs. (sersic-intensity), (sersicLtot)
+ *   GM_SERSIC   x0 y0 mag r_e n q pa B      Sec. 4.1, eqs. (sersic-intensity), (sersicLtot);
+ *               B: boxiness of eq. (r) (0 = ellipse; the generalised radius
+ *               (|X|^(B+2) + |Y/q|^(B+2))^(1/(B+2)) and r_box of eq. (rbox)
+ *               otherwise), fitted within [-0.9, 2]; a model whose B is free
+ *               or fixed at a value other than 0 runs for a single Sersic with
+ *               a flat sky (or none) only
  *   GM_EXPDISK  x0 y0 mag r_s q pa          Sec. 4.2.1, eqs. (expdisk_I), (expdiskI0)
  *   GM_FERRER   x0 y0 mag r_out q pa a b    Sec. 4.2.2 (a, b fixed)
  *   GM_KING     x0 y0 I0 r_c r_t q pa alpha Sec. 4.2.3 (alpha fixed)

@@ -284,10 +284,15 @@ int max_k(const CallInfo &ci)
 
 namespace {
 
-// Natural slots per profile type (index = type) and the LM slots among them
-// (the trailing ones are shape constants that stay fixed).
-const int kSlots[9] = {0, 7, 6, 8, 8, 6, 7, 1, 3};
+// Natural slots per profile type (index = type), the LM slots among them in
+// the plain families, and the first shape constant (trailing slots that stay
+// fixed).  The Sersic's eighth slot, the boxiness B of eq. (r), is no shape
+// constant: a Sersic with B free or not 0 runs in the boxy family.
+const int kSlots[9] = {0, 8, 6, 8, 8, 6, 7, 1, 3};
 const int kLmSlots[9] = {0, 7, 6, 6, 7, 6, 6, 1, 3};
+const int kShape0[9] = {0, 8, 6, 6, 7, 6, 6, 1, 3};
+
+bool boxy(const gm_component &c) { return c.type == GM_SERSIC && (c.param_index[7] >= 0 || c.fixed[7] != 0.0); }
 
 bool comp_ok(const gm_component &c, int p)
 {
@@ -313,7 +318,7 @@ void take(const gm_component &c, int s, int k, ModelArgs &ma)
 // Family tables (variants in order of preference), built once.
 enum {
     FAM_SERSIC = 1, FAM_EXPDISK, FAM_FERRER, FAM_KING, FAM_GAUSSIAN, FAM_MOFFAT, FAM_BULGEDISK, FAM_SERSICBAR,
-    FAM_SERSICTILT
+    FAM_SERSICTILT, FAM_SERSICBOX
 };
 
 FamilyOps family(int id, Variant a, Variant b)
@@ -349,9 +354,10 @@ const FamilyOps *family_table(int id)
         family(FAM_BULGEDISK, var_bulgedisk_2(), var_bulgedisk_3()),
         family(FAM_SERSICBAR, var_sersicbar_2(), var_sersicbar_3()),
         family(FAM_SERSICTILT, var_sersictilt_1(), var_sersictilt_2()),
+        family(FAM_SERSICBOX, var_sersicbox_1(), var_sersicbox_2()),
     };
     // indexed by id: the entries are in FAM_* order
-    static_assert(sizeof(tab) / sizeof(tab[0]) == FAM_SERSICTILT, "family table out of order");
+    static_assert(sizeof(tab) / sizeof(tab[0]) == FAM_SERSICBOX, "family table out of order");
     return &tab[id - 1];
 }
 
@@ -400,7 +406,7 @@ int match_model(const gm_model *m, Match &out)
     if (nrad < 1 || nrad > 2) return GM_EUNSUPPORTED;
     // shape constants (Ferrer a, b; King alpha; Moffat beta) must be fixed
     for (int i = 0; i < nrad; ++i)
-        for (int s = kLmSlots[rad[i]->type]; s < kSlots[rad[i]->type]; ++s)
+        for (int s = kShape0[rad[i]->type]; s < kSlots[rad[i]->type]; ++s)
             if (rad[i]->param_index[s] >= 0) return GM_EUNSUPPORTED;
     ModelArgs ma{};
     ma.p = m->p;
@@ -420,10 +426,17 @@ int match_model(const gm_model *m, Match &out)
     if (nrad == 1) {
         const gm_component &c = *rad[0];
         convolved = c.convolve != 0;
-        int ns = kLmSlots[c.type];
+        const bool bx = boxy(c);
+        int ns = bx ? 8 : kLmSlots[c.type];
         for (int s = 0; s < ns; ++s) take(c, s, s, ma);
         for (int s = ns; s < kSlots[c.type]; ++s) ma.cst[s - ns] = c.fixed[s];
-        if (sky && sky->type == GM_SKYPLANE) {
+        if (bx) {
+            // the boxy Sersic is compiled with a flat sky
+            if (sky && sky->type == GM_SKYPLANE) return GM_EUNSUPPORTED;
+            if (sky) take(*sky, 0, ns, ma);
+            nint = ns + 1;
+            ops = family_table(FAM_SERSICBOX);
+        } else if (sky && sky->type == GM_SKYPLANE) {
             // the tilted-plane sky is compiled for a single Sersic
             if (c.type != GM_SERSIC) return GM_EUNSUPPORTED;
             for (int s = 0; s < 3; ++s) take(*sky, s, ns + s, ma);
@@ -438,6 +451,7 @@ int match_model(const gm_model *m, Match &out)
         // Sersic + (exponential disk | Ferrer) with a shared centre, both convolved
         const gm_component *a = rad[0], *b = rad[1];
         if (sky && sky->type == GM_SKYPLANE) return GM_EUNSUPPORTED;
+        if (boxy(*a) || boxy(*b)) return GM_EUNSUPPORTED;
         if (b->type == GM_SERSIC) std::swap(a, b);
         if (a->type != GM_SERSIC || !(b->type == GM_EXPDISK || b->type == GM_FERRER) || !a->convolve ||
             !b->convolve)
@@ -464,6 +478,7 @@ int match_model(const gm_model *m, Match &out)
     out.single_type = nrad == 1 ? rad[0]->type : 0;
     out.has_sky = sky != nullptr;
     out.tilt = sky != nullptr && sky->type == GM_SKYPLANE;
+    out.box = nrad == 1 && boxy(*rad[0]);
     return GM_OK;
 }
 

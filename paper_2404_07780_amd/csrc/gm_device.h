@@ -20,7 +20,7 @@ constexpr float kDMag = -0.921034037197618f;   // d ln F / d m = -0.4 ln 10
 // Kinds of LM variables: centres, magnitudes, amplitudes, axis ratio and sky
 // are used as they are; positive scales and the Sersic index through their
 // natural log; position angles in radians (degrees at the interface).
-enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY, KSKYG };
+enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY, KSKYG, KBOX };
 
 __host__ __device__ inline double nat_to_u(int kind, double p)
 {
@@ -388,6 +388,106 @@ struct Sersic {
     {
         v[0] = xc; v[1] = yc; v[2] = m; v[3] = nrad > 1 ? 0.5 * r0 : r0; v[4] = nrad > 1 ? 4.0 : 2.0;
         v[5] = q0; v[6] = pa0;
+    }
+};
+
+// Boxy Sersic (Sec. 4.1, eqs. (r) and (rbox)): the Sersic law of the
+// generalised radius r = (|X|^c + |Y/q|^c)^(1/c), c = B + 2, in the frame
+// rotated by the position angle, and I_e multiplied by
+// r_box = pi c / (2 beta(1/c, 1/c)).  Slots x0 y0 mag ln r_e ln n q theta B.
+// With G = d ln I / d ln r = -b z / n (z = (r / r_e)^(1/n)):
+//   d ln r / dX = A / (S X), d ln r / dY = Bq / (S Y), A = |X|^c,
+//   Bq = |Y/q|^c, S = A + Bq (0 on an axis: c > 1);
+//   d ln r / dq = -Bq / (q S);
+//   d ln r / dc = -ln S / c^2 + (A ln|X| + Bq ln|Y/q|) / (c S);
+//   d ln r_box / dc = 1/c + 2 (psi(1/c) - psi(2/c)) / c^2.
+struct SersicBox {
+    struct K : Sersic::K {
+        double c, ic, iq;
+        float cf, icf, dlrboxf;
+    };
+    static constexpr int NS = 8, IQ = 5, ITH = 6, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s) { return s == 7 ? KBOX : Sersic::kind(s); }
+    __device__ static void prep(const double *u, const double *cst, double m0, int H, int W, int osf, int osw,
+                                int lane, K &k)
+    {
+        Sersic::prep(u, cst, m0, H, W, osf, osw, lane, k);
+        const double c = u[7] + 2.0, ic = 1.0 / c;
+        const double lnrbox = log(0.5 * kPi * c) - (2.0 * lgamma(ic) - lgamma(2.0 * ic));
+        k.lnIe += lnrbox;
+        k.lnIe2f = (float)(k.lnIe * kLog2e);
+        k.c = c;
+        k.ic = ic;
+        k.iq = 1.0 / u[5];
+        k.cf = (float)c;
+        k.icf = (float)ic;
+        k.dlrboxf = (float)(ic + 2.0 * (digamma(ic) - digamma(2.0 * ic)) * ic * ic);
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        const Geo &g = k.g;
+        float I, z, L2, Xf, Yf, lx, ly, lq, lc, gmask = 1.0f;
+        if constexpr (F64) {
+            const double X = g.c * dx + g.s * dy, Y = -g.s * dx + g.c * dy;
+            const double ax = fabs(X), ay = fabs(Y) * k.iq;
+            const double la = log(ax), lb = log(ay);
+            const double A = exp(k.c * la), Bq = exp(k.c * lb), S = A + Bq;
+            const double lS = log(S);
+            double L = 2.0 * lS * k.ic - k.lnre2;              // ln(r^2 / r_e^2)
+            const double fl = -27.631021115928547 - k.lnre2;   // r^2 >= 1e-12 px^2
+            if (!(L >= fl)) {
+                L = fl;
+                gmask = 0.0f;
+            }
+            const double zd = exp(L * k.inv2n);
+            I64 = exp(k.lnIe - k.b * (zd - 1.0));
+            I = (float)I64;
+            z = (float)zd;
+            L2 = (float)(L * kLog2e);
+            Xf = (float)X;
+            Yf = (float)Y;
+            lx = X != 0.0 ? (float)(A / (S * X)) : 0.0f;
+            ly = Y != 0.0 ? (float)(Bq / (S * Y)) : 0.0f;
+            lq = (float)(-Bq * k.iq / S);
+            lc = (float)(-lS * k.ic * k.ic + ((ax > 0.0 ? A * la : 0.0) + (ay > 0.0 ? Bq * lb : 0.0)) * k.ic / S);
+        } else {
+            const float dxf = (float)dx, dyf = (float)dy;
+            Xf = g.cf * dxf + g.sf * dyf;
+            Yf = -g.sf * dxf + g.cf * dyf;
+            const float ax = fabsf(Xf), ay = fabsf(Yf) * g.iqf;
+            const float la2 = __log2f(ax), lb2 = __log2f(ay);
+            const float A = exp2f(k.cf * la2), Bq = exp2f(k.cf * lb2), S = A + Bq;
+            const float lS2 = __log2f(S);
+            L2 = 2.0f * lS2 * k.icf - k.l2re2f;                 // log2(r^2 / r_e^2)
+            const float fl = -39.863137f - k.l2re2f;
+            if (!(L2 >= fl)) {
+                L2 = fl;
+                gmask = 0.0f;
+            }
+            z = exp2f(L2 * k.inv2nf);
+            I = exp2f(k.lnIe2f - k.b2f * (z - 1.0f));
+            I64 = I;
+            lx = Xf != 0.0f ? A / (S * Xf) : 0.0f;
+            ly = Yf != 0.0f ? Bq / (S * Yf) : 0.0f;
+            lq = -Bq * g.iqf / S;
+            lc = (float)kLn2 * (-lS2 * k.icf * k.icf + ((ax > 0.0f ? A * la2 : 0.0f) + (ay > 0.0f ? Bq * lb2 : 0.0f)) * k.icf / S);
+        }
+        const float gd = I * (-2.0f * k.bf * z * k.inv2nf) * gmask;     // I d ln I / d ln r
+        d[0] = gd * (-g.cf * lx + g.sf * ly);
+        d[1] = gd * (-g.sf * lx - g.cf * ly);
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + k.bnf * z);
+        d[4] = I * (k.cnf - k.nbpf * z + k.bl2nf * z * L2);
+        d[5] = gd * lq - I * g.iqf;
+        d[6] = gd * (Yf * lx - Xf * ly);
+        d[7] = I * k.dlrboxf + gd * lc;
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double pk,
+                                 int nrad, double *v)
+    {
+        Sersic::guess(xc, yc, m, r0, q0, pa0, pk, nrad, v);
+        v[7] = 0.0;
     }
 };
 
@@ -877,6 +977,7 @@ struct FamPair {
 
 using FamSersic = FamSingle<Sersic>;
 using FamSersicTilt = FamSingle<Sersic, true>;
+using FamSersicBox = FamSingle<SersicBox>;
 using FamBulgeDisk = FamPair<Sersic, ExpDisk>;
 using FamSersicBar = FamPair<Sersic, Ferrer>;
 

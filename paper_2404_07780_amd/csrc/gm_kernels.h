@@ -910,6 +910,7 @@ __device__ inline double clamp_var(int k, double v, int H, int W)
     case KSCALE: return fmin(fmax(v, log(0.1)), log(big));
     case KN: return fmin(fmax(v, log(0.2)), log(10.0));
     case KQ: return fmin(fmax(v, 0.05), 20.0);
+    case KBOX: return fmin(fmax(v, -0.9), 2.0);
     default: return v;
     }
 }

@@ -460,6 +460,8 @@ Variant var_gaussian_2();
 Variant var_moffat_2();
 Variant var_sersictilt_1();
 Variant var_sersictilt_2();
+Variant var_sersicbox_1();
+Variant var_sersicbox_2();
 
 // A caller's gm_model matched against the compiled families (gm_abi.hip).
 struct Match {
@@ -468,6 +470,7 @@ struct Match {
     int single_type = 0;      // profile type of a one-component model, else 0
     bool has_sky = false;
     bool tilt = false;        // the sky is the tilted plane
+    bool box = false;         // a Sersic with boxiness (B free or not 0)
 };
 int match_model(const gm_model *m, Match &out);
 int check_batch(const gm_batch *b, bool convolved);

@@ -659,7 +659,7 @@ int adamw_step(const gm_mlp *m, int64_t step, const gm_adamw *o, hipStream_t st)
 // proposal encodes.
 int check_proposal_model(const Match &mt)
 {
-    if (mt.single_type != GM_SERSIC || !mt.has_sky || mt.tilt) return GM_EUNSUPPORTED;
+    if (mt.single_type != GM_SERSIC || !mt.has_sky || mt.tilt || mt.box) return GM_EUNSUPPORTED;
     for (int k = 0; k < 8; ++k)
         if (mt.ci.ma.col[k] < 0) return GM_EUNSUPPORTED;
     return GM_OK;

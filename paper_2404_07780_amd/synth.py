@@ -58,6 +58,15 @@ MODEL_SPECS: Dict[str, dict] = {
         ],
         names=["x0", "y0", "mag", "re", "n", "q", "pa", "sky"],
     ),
+    # single boxy Sersic (B of eq. (r) free) + sky: x0 y0 mag re n q pa box sky
+    "sersic_box": dict(
+        p=9,
+        comps=[
+            (SERSIC, 1, [0, 1, 2, 3, 4, 5, 6, 7], []),
+            (SKY, 0, [8], []),
+        ],
+        names=["x0", "y0", "mag", "re", "n", "q", "pa", "box", "sky"],
+    ),
     # single Sersic + the tilted-plane sky of Appendix D: ... sky kx ky
     "sersic_tilt": dict(
         p=10,
@@ -111,6 +120,7 @@ MODEL_SPECS: Dict[str, dict] = {
 FLUX_COLUMNS = {
     "sersic": [("mag", 2)],
     "sersic_tilt": [("mag", 2)],
+    "sersic_box": [("mag", 2)],
     "bulgedisk": [("mag", 2), ("mag", 7)],
     "sersicbar": [("mag", 2), ("mag", 7)],
     "king": [("amp", 2)],

@@ -67,3 +67,18 @@ def param_parity(names, gpu, ref, sky_sigma: float = 1.0, rel: float = 1e-4):
         worst[k] = r
         ok[k] = r <= 1.0
     return ok, worst
+
+
+def oracle_box_batch(config: str, n: int, seed: int = 0, lo: float = -0.5, hi: float = 1.0) -> S.Batch:
+    """Galaxies of `config` drawn as single Sersics, given a boxiness B ~ U(lo, hi)
+    (eq. (r)), rendered by the oracle with model sersic_box and noised."""
+    b = S.draw(config, n, seed=seed)
+    rng = np.random.default_rng(seed + 1000)
+    B = rng.uniform(lo, hi, b.n)
+    b.truth = np.concatenate([b.truth[:, :7], B[:, None], b.truth[:, 7:]], axis=1)
+    b.model = "sersic_box"
+    m = from_spec(b.model)
+    ut = S.unit_truth(b)
+    units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
+                            for g in range(b.n)])
+    return S.finish(b, units)

@@ -90,6 +90,10 @@ WORKLOADS = {
                       "betas 0.9/0.999) on 8192 held-out single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px "
                       "on 15x15, unit-sigma noise, from the moment start; LM on the same batch and kernels as "
                       "context"),
+    "box": dict(n=8192, cfg="sersic64", seed=0, box=True,
+                desc="8192 boxy and discy single-Sersic galaxies (boxiness B ~ U(-0.5, 1) of the generalised "
+                     "radius), 64x64, Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise; LM with B free from "
+                     "the moment start (B = 0)"),
     "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
                       desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
                            "25x25, Poisson + read noise, LM from moment-based start"),
@@ -100,10 +104,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_batch(cfg: str, n: int, seed: int):
+def make_batch(cfg: str, n: int, seed: int, box: bool = False):
     """Draw, render at unit flux with the HIP forward model, add noise: on the
-    device (Philox) for the unit-sigma workload, on the host otherwise."""
+    device (Philox) for the unit-sigma workload, on the host otherwise.  With
+    box the Sersics get a boxiness B ~ U(-0.5, 1) (model sersic_box)."""
     b = S.draw(cfg, n, seed=seed)
+    if box:
+        B = np.random.default_rng(seed + 1000).uniform(-0.5, 1.0, b.n)
+        b.truth = np.concatenate([b.truth[:, :7], B[:, None], b.truth[:, 7:]], axis=1)
+        b.model = "sersic_box"
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
     unused = torch.empty(b.npix, dtype=torch.float32, device="cuda")
     db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, unused, unused, b.psf)
@@ -131,17 +140,17 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
     return 2.0 * hw * k2 * npl, 2.0 * hw * (p * (p + 1) / 2 + p + 1)
 
 
-def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20):
+def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20, box: bool = False):
     """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
     noised on the host), all host cores, LM from its own moment start; the GPU
     fits of the same data (plain, and learned when a network is given) are
     judged against it."""
     import oracle as O
-    from tests.gpu_helpers import oracle_batch, param_parity
+    from tests.gpu_helpers import oracle_batch, oracle_box_batch, param_parity
     from tests.oracle_models import from_spec
 
     ncores = len(os.sched_getaffinity(0))
-    b = oracle_batch(cfg, n_sample, seed=seed)
+    b = oracle_box_batch(cfg, n_sample, seed=seed) if box else oracle_batch(cfg, n_sample, seed=seed)
     om = from_spec(b.model)
     db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf)
     t0 = time.perf_counter()
@@ -516,11 +525,11 @@ def main():
         return adam_main(args, n, seed)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
-        args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32}.get(args.workload, 160)
+        args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32, "box": 256}.get(args.workload, 160)
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()
-    b, gm, db = make_batch(wl["cfg"], n, seed)
+    b, gm, db = make_batch(wl["cfg"], n, seed, box=wl.get("box", False))
     torch.cuda.synchronize()
     log(f"generated {n} galaxies ({b.npix / 1e6:.1f} Mpx) in {time.perf_counter() - t0:.1f} s")
     from paper_2404_07780_amd import tune
@@ -622,7 +631,8 @@ def main():
     cpu, parity = None, None
     if args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} galaxies")
-        cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp, args.proposal_max_iter)
+        cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp, args.proposal_max_iter,
+                                   box=wl.get("box", False))
 
     key = f"{args.workload}:{n}:{seed}:{source_hash()}"
     out = {

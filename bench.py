@@ -370,8 +370,9 @@ def adam_main(args, n: int, seed: int):
     wall, evs = timed(step, args.steps, args.warmup, "adam")
     ms = float(np.mean([evs[i][1].elapsed_time(evs[i][2]) for i in range(args.steps)]))
     ap_, ac, ast = [t.cpu().numpy() for t in out]
-    # Adam's evaluation: npl planes convolved, chi^2 and the gradient reduced (no normal matrix)
-    f_conv, _ = flops_per_eval(b, p, p - 1)
+    # Adam's evaluation by the adjoint: two convolutions (the light, then the weighted
+    # residual with the flipped PSF) and the chi^2 and gradient sums
+    f_conv, _ = flops_per_eval(b, p, 2)
     f_red = 2.0 * b.h.astype(np.float64) * b.w * (p + 1)
     flops = float(np.sum((f_conv + f_red) * (ADAM["steps"] + 1)))
     achieved = flops / (ms / 1e3) / 1e12

@@ -489,15 +489,14 @@ __device__ inline void boot_weights(const BootArgs &bt, int64_t pix0, float (&m)
 
 // One model evaluation at u (LDS): chi^2, g = J^T W r and A = J^T W J
 // (internal LM variables), written to out_chi2/out_g/out_A (LDS, A full
-// P x P; with WA false A is neither formed nor written).  All threads of the
-// workgroup call it.
-template <class F, int KT, int NG, bool WA = true>
+// P x P).  All threads of the workgroup call it.
+template <class F, int KT, int NG>
 __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &ba, const Meta &me, EvalShared<F> &sh,
                          float *planes, double *out_chi2, double *out_g, double *out_A,
                          const BootArgs &bt = BootArgs{0u, 0u, 0, -1})
 {
     constexpr int P = F::P;
-    constexpr int NR = 1 + P + (WA ? P * (P + 1) / 2 : 0);
+    constexpr int NR = 1 + P + P * (P + 1) / 2;
     const int H = me.h, W = me.w, K = me.k;
     const int tid = threadIdx.x;
     eval_prologue<F>(u, ma, H, W, sh, planes);
@@ -538,13 +537,11 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
                     for (int k = 0; k < P; ++k) {
                         const float Jk = jac_at<F>(k, t, acc0, acc, fdx, fdy);
                         red[k] = fmaf(wr, Jk, red[k]);
-                        if constexpr (WA) {
-                            const float wj = wgt * Jk;
+                        const float wj = wgt * Jk;
 #pragma unroll
-                            for (int l = 0; l <= k; ++l) {
-                                const float Jl = jac_at<F>(l, t, acc0, acc, fdx, fdy);
-                                red[P + k * (k + 1) / 2 + l] = fmaf(wj, Jl, red[P + k * (k + 1) / 2 + l]);
-                            }
+                        for (int l = 0; l <= k; ++l) {
+                            const float Jl = jac_at<F>(l, t, acc0, acc, fdx, fdy);
+                            red[P + k * (k + 1) / 2 + l] = fmaf(wj, Jl, red[P + k * (k + 1) / 2 + l]);
                         }
                     }
                 }
@@ -1192,76 +1189,6 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
             if (fa.err)
                 fit_errors<F>(s.A, s.g, s.u, s.freev, ma, fa.err + (int64_t)g * ma.p,
                               reinterpret_cast<double *>(planes));
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------- gradient descent (Adam)
-// The paper's own fitter (Sec. 5.1: gradient descent, Adam in its examples)
-// on the same evaluation: chi^2 and g = J^T W r at u give the gradient
-// d chi^2 / d u = -2 g in the LM variables; Adam (Kingma and Ba 2015) takes
-// `steps` steps with bias-corrected moments, the iterate clamped to the LM
-// bounds after each, fixed slots untouched.  The reported chi^2 is that of a
-// last evaluation at the final iterate; status GM_ST_MAXITER (all steps
-// taken) or GM_ST_NONFINITE.
-struct AdamArgs {
-    const int *order;
-    int n_gal;
-    int *queue;
-    double *params, *chi2;
-    int *status;
-    int steps;
-    double lr, beta1, beta2, eps;
-};
-
-template <class F, int KT, int NG>
-__global__ __launch_bounds__(NT, (min_wg<F, KT>())) void adam_fit_kernel(ModelArgs ma, BatchArgs ba, AdamArgs aa)
-{
-    extern __shared__ float4 dyn_lds[];
-    float *planes = reinterpret_cast<float *>(dyn_lds);
-    __shared__ EvalShared<F> esh;
-    __shared__ LMShared<F> s;
-    constexpr int P = F::P;
-    const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s.gal = atomicAdd(aa.queue, 1);
-        __syncthreads();
-        const int qi = uniform(s.gal);
-        if (qi >= aa.n_gal) break;
-        const int g = uniform(aa.order[qi]);
-        const Meta me = ba.meta[g];
-        if (tid == 0) {
-            load_u<F>(s, ma, aa.params + (int64_t)g * ma.p);
-            clamp_u<F>(s.u, me.h, me.w);
-        }
-        __syncthreads();
-        // moments of lane k (k < P): registers of the first wave
-        double m1 = 0.0, m2 = 0.0, b1t = 1.0, b2t = 1.0;
-        bool bad = false;
-        for (int t = 1; t <= aa.steps && !bad; ++t) {
-            evaluate<F, KT, NG, false>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
-            bad = !isfinite(s.chi2);
-            if (!bad && tid < P && s.freev[tid]) {
-                const double grad = -2.0 * s.g[tid];
-                m1 = aa.beta1 * m1 + (1.0 - aa.beta1) * grad;
-                m2 = aa.beta2 * m2 + (1.0 - aa.beta2) * grad * grad;
-                b1t *= aa.beta1;
-                b2t *= aa.beta2;
-                const double mh = m1 / (1.0 - b1t), vh = m2 / (1.0 - b2t);
-                s.u[tid] = clamp_var<F>(tid, s.u[tid] - aa.lr * mh / (sqrt(vh) + aa.eps), me.h, me.w);
-            }
-            __syncthreads();
-        }
-        if (!bad) evaluate<F, KT, NG, false>(s.u, ma, ba, me, esh, planes, &s.chi2, s.g, s.A);
-        if (tid == 0) {
-            double nat[P];
-            canonical_nat<F>(s.u, s.freev, nat);
-            double *out = aa.params + (int64_t)g * ma.p;
-            for (int k = 0; k < P; ++k)
-                if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
-            aa.chi2[g] = s.chi2;
-            aa.status[g] = (bad || !isfinite(s.chi2)) ? GM_ST_NONFINITE : GM_ST_MAXITER;
         }
         __syncthreads();
     }

@@ -156,19 +156,14 @@ int launch_fit(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const FitArg
     return hip_rc(hipGetLastError());
 }
 
+// Gradient-descent fitter (gm_adam.h, included at the end)
+struct AdamArgs;
 template <class F, int NG, int KT>
-int launch_adam(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const AdamArgs &aa, size_t lds, int wpc,
-                hipStream_t st)
-{
-    auto kern = adam_fit_kernel<F, KT, NG>;
-    int per_cu;
-    int rc = prepare(kern, lds, &per_cu);
-    if (rc) return rc;
-    if (wpc > 0) per_cu = std::min(per_cu, wpc);
-    int grid = std::min(aa.n_gal, per_cu * c->num_cu);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, ma, ba, aa);
-    return hip_rc(hipGetLastError());
-}
+int launch_adam(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, AdamArgs aa, size_t lds, int wpc,
+                int64_t psf_len, int64_t max_px, hipStream_t st);
+template <class F, int NG, int... KTS>
+int run_adam(gm_ctx *c, const CallInfo &ci, const gm_adam_opts *o, double *params, double *chi2, int32_t *status,
+             hipStream_t st);
 
 template <class F, int NG, int KT>
 int launch_err(gm_ctx *c, const ModelArgs &ma, const BatchArgs &ba, const ErrArgs &ea, size_t lds, int wpc,
@@ -281,42 +276,6 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
         fa.boot_k1 = (uint32_t)(ex->boot_seed >> 32);
     }
     return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
-}
-
-template <class F, int NG, int... KTS>
-int run_adam(gm_ctx *c, const CallInfo &ci, const gm_adam_opts *o, double *params, double *chi2, int32_t *status,
-             hipStream_t st)
-{
-    const gm_batch *b = ci.b;
-    size_t lds;
-    int rc = check_lds<F, NG>(max_k(ci), &lds);
-    if (rc) return rc;
-    std::vector<int> order(b->n_gal);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(b->n_gal);
-    for (int g = 0; g < b->n_gal; ++g) {
-        double k = ci.convolved ? b->psf_k[g] : 1.0;
-        cost[g] = (double)b->h[g] * b->w[g] * k * k;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    Staged sg;
-    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)b->n_gal, st, &sg);
-    if (rc) return rc;
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
-    if (hipGetLastError() != hipSuccess) return GM_EHIP;
-    AdamArgs aa{};
-    aa.order = reinterpret_cast<const int *>(sg.extra);
-    aa.n_gal = b->n_gal;
-    aa.queue = sg.queue;
-    aa.params = params;
-    aa.chi2 = chi2;
-    aa.status = status;
-    aa.steps = o->steps;
-    aa.lr = o->lr;
-    aa.beta1 = o->beta1;
-    aa.beta2 = o->beta2;
-    aa.eps = o->eps;
-    return Dispatch<F, NG, KTS...>::adam(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), aa, lds, ci.wpc, st);
 }
 
 template <class F, int NG, int... KTS>
@@ -495,3 +454,5 @@ struct Scoped {
 };
 
 }  // namespace gm
+
+#include "gm_adam.h"

@@ -47,10 +47,10 @@ METRIC = "galaxies fitted/s at <=1e-4 rel param err vs oracle; learned-init vs p
 # (scaled by the counts of a 1 GiB copy: FETCH x 2.0, WRITE x 1.0), keyed by
 # workload and the hash of the library sources they were taken with.
 TRAFFIC = {
-    # profiles/lm_fit_learned65536.md: the two LM launches of one learned step
-    "learned:65536:2:6acea46f26ff9d31": 3.568239e+09,
+    # profiles/lm_fit_learned65536.md: the LM launch of one learned step
+    "learned:65536:2:8fd2fcc69029f613": 3.719658e+09,
     # profiles/lm_fit_uneven8192.md: one LM launch
-    "uneven:8192:0:6acea46f26ff9d31": 1.305287e+10,
+    "uneven:8192:0:8fd2fcc69029f613": 1.308382e+10,
 }
 
 
@@ -90,6 +90,11 @@ WORKLOADS = {
                       "betas 0.9/0.999) on 8192 held-out single-Sersic galaxies, 64x64, Gaussian PSF FWHM 1.5 px "
                       "on 15x15, unit-sigma noise, from the moment start; LM on the same batch and kernels as "
                       "context"),
+    "mixed": dict(n=262144, cfg="mixed", seed=0,
+                  desc="262144 galaxies in chunks of 16384, square cutouts log-uniform 64-192 px: 60% single "
+                       "Sersic (learned proposal with moment-start fallback), 20% Sersic + Ferrer bar, 10% King, "
+                       "10% unconvolved Moffat point source (moment start); per-galaxy Moffat PSF 25x25, Poisson + "
+                       "5 e- read noise, at least 5% of pixels masked in elliptical blobs; all chunks resident"),
     "box": dict(n=8192, cfg="sersic64", seed=0, box=True,
                 desc="8192 boxy and discy single-Sersic galaxies (boxiness B ~ U(-0.5, 1) of the generalised "
                      "radius), 64x64, Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise; LM with B free from "
@@ -416,6 +421,172 @@ def adam_main(args, n: int, seed: int):
     print(json.dumps(outj))
 
 
+MIXED_CHUNK = 16384
+
+
+def _draw_mixed_chunk(task):
+    n, seed, start = task
+    return S.draw_mixed(n, seed=seed, start=start)
+
+
+def mixed_draw(n: int, seed: int):
+    """Host part of the mixed workload (parameters, PSFs, masks), one chunk
+    per worker process; run before the GPU is touched (forked workers)."""
+    import multiprocessing as mp
+
+    tasks = [(min(MIXED_CHUNK, n - s), seed, s) for s in range(0, n, MIXED_CHUNK)]
+    nproc = max(1, min(16, len(os.sched_getaffinity(0)), len(tasks)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(nproc) as pool:
+        chunks = []
+        for i, c in enumerate(pool.imap(_draw_mixed_chunk, tasks)):
+            chunks.append(c)
+            log(f"mixed: chunk {i + 1}/{len(tasks)} drawn ({time.perf_counter() - t0:.1f} s)")
+    return chunks
+
+
+def mixed_upload(b: S.Batch, seed: int):
+    """Render a drawn batch at unit flux with the HIP forward model and add the
+    recipe's noise on the device: F from the peak SNR (as in synth.finish),
+    D = Poisson(F unit + sky) + N(0, 5^2), sigma^2 = F unit + sky + 25."""
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    dev = torch.device("cuda")
+    unused = torch.empty(b.npix, dtype=torch.float32, device=dev)
+    db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, unused, unused, b.psf,
+                 omega=torch.from_numpy(b.omega).to(dev))
+    units = G.gm_model_image(gm, db, S.unit_truth(b))
+    peak = np.maximum.reduceat(units.cpu().numpy(), b.img_off.astype(np.int64))
+    var0 = b.sky + S.READ_NOISE ** 2
+    P = 0.5 * (b.snr ** 2 + np.sqrt(b.snr ** 4 + 4.0 * b.snr ** 2 * var0))
+    F = P / peak
+    npx = (b.h.astype(np.int64) * b.w)
+    Fp = torch.from_numpy(np.repeat(F, npx).astype(np.float32)).to(dev)
+    sky = torch.from_numpy(np.repeat(b.sky, npx).astype(np.float32)).to(dev)
+    m = Fp * units + sky
+    del units, Fp, sky
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    data = torch.poisson(m, generator=gen) + S.READ_NOISE * torch.randn(m.shape, device=dev, generator=gen)
+    db.data = data
+    db.sigma = torch.sqrt(m + S.READ_NOISE ** 2)
+    return gm, db
+
+
+def mixed_main(args, n: int, seed: int, chunks):
+    """--workload mixed: every chunk resident in HBM, one step = every chunk's
+    batches fitted (Sersic: learned proposal + fallback; the others: moment
+    start + LM), each step timed whole."""
+    mlp, train_info = train_network(args.train_n, args.epochs, args.train_batch)
+    batches = []
+    t0 = time.perf_counter()
+    for ci, parts in enumerate(chunks):
+        for kind in S.MIXED_KINDS:
+            if kind in parts:
+                b = parts[kind]
+                gm, db = mixed_upload(b, seed * 1000003 + ci * 16 + S.MIXED_KINDS.index(kind))
+                batches.append((kind, b, gm, db))
+        log(f"mixed: chunk {ci + 1}/{len(chunks)} rendered and noised on the device "
+            f"({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    ctx = G.context()
+    outs = []
+    for kind, b, gm, db in batches:
+        dev = db.device
+        o = (torch.empty(b.n, gm.p, dtype=torch.float64, device=dev), torch.empty(b.n, dtype=torch.float64, device=dev),
+             torch.empty(b.n, dtype=torch.int32, device=dev), torch.empty(b.n, dtype=torch.int32, device=dev),
+             torch.empty(b.n, dtype=torch.int32, device=dev))
+        outs.append(o)
+
+    def step(ev):
+        if ev:
+            ev[0].record()
+        for (kind, b, gm, db), o in zip(batches, outs):
+            if kind == "sersic":
+                G.gm_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter, ctx=ctx, out=o)
+            else:
+                guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
+                G.gm_fit_batch(gm, db, guess, ctx=ctx, out=o[:4])
+        if ev:
+            ev[1].record()
+
+    wall, evs = timed(step, args.steps, args.warmup, "mixed")
+    ms = float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)]))
+    per_kind = {}
+    for (kind, b, gm, db), o in zip(batches, outs):
+        st = o[3].cpu().numpy()
+        d = per_kind.setdefault(kind, dict(n=0, converged=0, iters=0.0, fallback=0))
+        d["n"] += int(b.n)
+        d["converged"] += int((st == G.ST_CONVERGED).sum())
+        d["iters"] += float(o[2].cpu().numpy().sum())
+        if kind == "sersic":
+            d["fallback"] += int((o[4].cpu().numpy() != 0).sum())
+    for d in per_kind.values():
+        d["converged_frac"] = d["converged"] / max(d["n"], 1)
+        d["mean_iters"] = d["iters"] / max(d["n"], 1)
+        del d["iters"]
+    cpu = parity = None
+    if args.cpu_sample != 0:
+        ns = 256 if args.cpu_sample is None else args.cpu_sample
+        log(f"cpu baseline: oracle on mixed galaxies 0..{ns - 1}")
+        cpu, parity = mixed_baseline(ns, seed, mlp, args.proposal_max_iter)
+    outj = {
+        "metric": "galaxies fitted/s (mixed profiles, learned-init LM for the Sersic parts, plain LM otherwise)",
+        "value": n / (wall / args.steps), "unit": "galaxies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"mixed: {WORKLOADS['mixed']['desc']}", "n_gal": n, "seed": seed,
+                   "chunk": MIXED_CHUNK, "batches": len(batches), "launch": "eager calls, library default schedules",
+                   "proposal_max_iter": args.proposal_max_iter},
+        "roofline": None,
+        "gpu_ms_per_step": ms,
+        "per_kind": per_kind,
+        "training": train_info,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(outj))
+
+
+def mixed_baseline(n_sample: int, seed: int, mlp, pmi: int):
+    """FP64 oracle on mixed galaxies 0..n_sample-1 (rendered and noised on the
+    host by the recipe), moment start + LM on all host cores; the GPU fits the
+    same images (learned + fallback for the Sersics, moment start otherwise)
+    and is judged per kind: convergence of each side, parity of galaxies both
+    converged."""
+    import oracle as O
+    from tests.gpu_helpers import oracle_mixed, param_parity
+    from tests.oracle_models import from_spec
+
+    ncores = len(os.sched_getaffinity(0))
+    mixed = oracle_mixed(n_sample, seed=seed)
+    dt = 0.0
+    out = {}
+    for kind, b in mixed.items():
+        om = from_spec(b.model)
+        gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+        t0 = time.perf_counter()
+        ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, omega=b.omega)
+        rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
+                                     omega=b.omega, nthreads=ncores)
+        dt += time.perf_counter() - t0
+        db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf, omega=b.omega)
+        if kind == "sersic":
+            gp, gc, gn, gs, _ = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=pmi)]
+        else:
+            start, _ = G.gm_default_guess(gm, db)
+            gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+        names = S.MODEL_SPECS[b.model]["names"]
+        both = (gs == 0) & (rs == 0)
+        npass = sum(int(param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))[0].all())
+                    for g in np.where(both)[0])
+        out[kind] = dict(n=int(b.n), gpu_converged=int((gs == 0).sum()), oracle_converged=int((rs == 0).sum()),
+                         both_converged=int(both.sum()), pass_1e4=int(npass))
+    cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
+               sample=f"mixed galaxies 0..{n_sample - 1} (rendered and noised on the host), moment start and LM, "
+                      f"{dt:.1f} s")
+    return cpu, dict(sample=n_sample, per_kind=out)
+
+
 def timed(step, steps: int, warmup: int, name: str):
     for i in range(warmup):
         step(None)
@@ -506,6 +677,11 @@ def main():
         print("bench.py measures one GPU only: the fitter shards by galaxy with no communication, "
               "and multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+    mixed_chunks = None
+    if args.workload == "mixed":
+        # host-side drawing in forked workers, before anything touches the GPU
+        mixed_chunks = mixed_draw(args.n or WORKLOADS["mixed"]["n"],
+                                  WORKLOADS["mixed"]["seed"] if args.seed is None else args.seed)
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
@@ -524,6 +700,8 @@ def main():
         return bootstrap_main(args, n, seed)
     if args.workload == "adam":
         return adam_main(args, n, seed)
+    if args.workload == "mixed":
+        return mixed_main(args, n, seed, mixed_chunks)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
         args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32, "box": 256}.get(args.workload, 160)

@@ -174,14 +174,15 @@ double orc_sersic_db(double n)
  * natural log for every positive scale and for the Sersic index; radians for
  * the position angle (the paper's `log=True` / `angle=True` flags,
  * Appendix A, extended to the other scales). */
-enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE, K_SKYGRAD, K_BOX };
+enum { K_NONE = 0, K_X0, K_Y0, K_MAG, K_AMP, K_SCALE, K_N, K_Q, K_PA, K_SKY, K_SHAPE, K_SKYGRAD, K_BOX,
+       K_FA, K_FB, K_KAL };
 
 static const int slot_kind[9][ORC_MAX_SLOTS] = {
     /* 0 unused */ {0},
     /* SERSIC   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_N, K_Q, K_PA, K_BOX},
     /* EXPDISK  */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_NONE, K_NONE},
-    /* FERRER   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_SHAPE, K_SHAPE},
-    /* KING     */ {K_X0, K_Y0, K_AMP, K_SCALE, K_SCALE, K_Q, K_PA, K_SHAPE},
+    /* FERRER   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_FA, K_FB},
+    /* KING     */ {K_X0, K_Y0, K_AMP, K_SCALE, K_SCALE, K_Q, K_PA, K_KAL},
     /* GAUSSIAN */ {K_X0, K_Y0, K_AMP, K_SCALE, K_Q, K_PA, K_NONE, K_NONE},
     /* MOFFAT   */ {K_X0, K_Y0, K_MAG, K_SCALE, K_Q, K_PA, K_SHAPE, K_NONE},
     /* SKY      */ {K_SKY, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE, K_NONE},
@@ -242,11 +243,12 @@ static void comp_values(const orc_model *m, int c, const double *params, double 
         v[s] = cp->idx[s] >= 0 ? params[cp->idx[s]] : cp->fixed[s];
 }
 
-/* natural -> LM variable and back, per column kind */
+/* natural -> LM variable and back, per column kind (Ferrer a and King alpha,
+ * positive shape exponents, through their log like the scales) */
 static double to_u(int kind, double p)
 {
     switch (kind) {
-    case K_SCALE: case K_N: return log(p);
+    case K_SCALE: case K_N: case K_FA: case K_KAL: return log(p);
     case K_PA: return p * ORC_PI / 180.0;
     default: return p;
     }
@@ -254,7 +256,7 @@ static double to_u(int kind, double p)
 static double from_u(int kind, double u)
 {
     switch (kind) {
-    case K_SCALE: case K_N: return exp(u);
+    case K_SCALE: case K_N: case K_FA: case K_KAL: return exp(u);
     case K_PA: return u * 180.0 / ORC_PI;
     default: return u;
     }
@@ -263,7 +265,7 @@ static double from_u(int kind, double u)
 static double dp_du(int kind, double p)
 {
     switch (kind) {
-    case K_SCALE: case K_N: return p;
+    case K_SCALE: case K_N: case K_FA: case K_KAL: return p;
     case K_PA: return 180.0 / ORC_PI;
     default: return 1.0;
     }
@@ -284,6 +286,8 @@ typedef struct {
     /* others */
     double scale, scale2, a_f, b_f, alpha, beta, rd;
     double kA, dkA_dlnrc, dkA_dlnrt;   /* King: T^(-1/alpha) and derivatives */
+    double kT;                         /* King: T = 1 + (r_t / r_c)^2 */
+    double fc2;                        /* Ferrer: 1 + 2 / (2 - b) */
     double xc, yc;               /* plane sky: the cutout's geometric centre */
     double cbox, dlrbox;         /* Sersic: exponent c = B + 2 of eq. (r), d ln r_box / dc */
 } comp_prep;
@@ -331,6 +335,7 @@ static void prep_component(const orc_model *m, int c, const double *params, comp
         cp->scale = rout; cp->a_f = a; cp->b_f = bb;
         double c2 = 1.0 + 2.0 / (2.0 - bb);
         double lbeta = lgamma(a) + lgamma(c2) - lgamma(a + c2);
+        cp->fc2 = c2;
         /* I0 = F / (pi q rout^2 a beta(a, 1 + 2/(2-b))) */
         cp->lnamp = lnF - log(ORC_PI * q * rout * rout * a) - lbeta;
         break;
@@ -339,6 +344,7 @@ static void prep_component(const orc_model *m, int c, const double *params, comp
         double rc = v[3], rt = v[4], al = v[7];
         cp->scale = rc; cp->scale2 = rt; cp->alpha = al;
         double T = 1.0 + (rt / rc) * (rt / rc);
+        cp->kT = T;
         cp->kA = pow(T, -1.0 / al);
         /* dA/dln rc = 2 A (T-1) / (alpha T);  dA/dln rt = -2 A (T-1) / (alpha T) */
         cp->dkA_dlnrc = 2.0 * cp->kA * (T - 1.0) / (al * T);
@@ -453,6 +459,12 @@ static void comp_point(const comp_prep *cp, double x, double y, double *I, doubl
         dl_dq_direct = -1.0 / q;
         dI[2] = -0.4 * ORC_LN10 * val;
         dI[3] = val * (-2.0 + a * e * u / omu);                  /* ln rout */
+        /* a (as ln a): d ln I / da = ln(1 - u) - 1/a - (psi(a) - psi(a + c2)), the last two
+         * from I0 = F / (pi q rout^2 a beta(a, c2)); b: u = (r/rout)^(2-b) gives
+         * d ln(1 - u) / db = (u / (1 - u)) ln(r / rout), and dc2/db = 2 / (2 - b)^2 */
+        double c2 = cp->fc2, lnr_ro = lnu / e;
+        dI[6] = val * a * (log(omu) - 1.0 / a - (orc_digamma(a) - orc_digamma(a + c2)));
+        dI[7] = val * (a * u / omu * lnr_ro - (orc_digamma(c2) - orc_digamma(a + c2)) * 2.0 / (e * e));
         break;
     }
     case ORC_KING: {
@@ -470,6 +482,10 @@ static void comp_point(const comp_prep *cp, double x, double y, double *I, doubl
         dI[2] = shape;                                           /* I0 */
         dI[3] = val * (al * cp->dkA_dlnrc / (1.0 - A) + al * (dS_dlnrc - cp->dkA_dlnrc) / Dd);
         dI[4] = val * (al * cp->dkA_dlnrt / (1.0 - A) - al * cp->dkA_dlnrt / Dd);
+        /* alpha (as ln alpha): ln(I/I0) = alpha [ln(S - A) - ln(1 - A)] with
+         * dS/dalpha = S ln s / alpha^2 and dA/dalpha = A ln T / alpha^2 */
+        double dS_da = S * log(s) / (al * al), dA_da = A * log(cp->kT) / (al * al);
+        dI[7] = val * al * (log(Dd / (1.0 - A)) + al * ((dS_da - dA_da) / Dd + dA_da / (1.0 - A)));
         break;
     }
     case ORC_GAUSSIAN: {
@@ -786,7 +802,8 @@ static void chol_inverse(int p, const double *L, double *inv)
  * converted to u): centres inside the cutout, positive scales in
  * [0.1, 2 max(H, W)] px, Sersic index in [0.2, 10], axis ratio in
  * [0.05, 20] (q > 1 is allowed during the fit and canonicalised at the end),
- * boxiness B in [-0.9, 2] (c = B + 2 in [1.1, 4]). */
+ * boxiness B in [-0.9, 2] (c = B + 2 in [1.1, 4]), Ferrer a in [0.1, 10] and
+ * b in [-1, 1.95], King alpha in [0.5, 10]. */
 static void clamp_u(const orc_model *m, int h, int w, double *u)
 {
     double big = 2.0 * (h > w ? h : w);
@@ -800,6 +817,9 @@ static void clamp_u(const orc_model *m, int h, int w, double *u)
         case K_N: lo = log(0.2); hi = log(10.0); break;
         case K_Q: lo = 0.05; hi = 20.0; break;
         case K_BOX: lo = -0.9; hi = 2.0; break;
+        case K_FA: lo = log(0.1); hi = log(10.0); break;
+        case K_FB: lo = -1.0; hi = 1.95; break;
+        case K_KAL: lo = log(0.5); hi = log(10.0); break;
         default: break;
         }
         if (u[k] < lo) u[k] = lo;
@@ -1194,11 +1214,11 @@ int orc_default_guess(const orc_model *m, int h, int w, const float *data, const
         case ORC_EXPDISK:
             v[0] = xc; v[1] = yc; v[2] = msplit; v[3] = r0 / 1.678347; v[4] = q0; v[5] = pa0;
             break;
-        case ORC_FERRER:
-            v[0] = xc; v[1] = yc; v[2] = msplit; v[3] = r0; v[4] = q0; v[5] = pa0;
+        case ORC_FERRER:    /* free a, b start at the values printed in Appendix C */
+            v[0] = xc; v[1] = yc; v[2] = msplit; v[3] = r0; v[4] = q0; v[5] = pa0; v[6] = 0.5; v[7] = 1.9;
             break;
         case ORC_KING:
-            v[0] = xc; v[1] = yc; v[2] = pk; v[3] = 0.5 * r0; v[4] = 4.0 * r0; v[5] = q0; v[6] = pa0;
+            v[0] = xc; v[1] = yc; v[2] = pk; v[3] = 0.5 * r0; v[4] = 4.0 * r0; v[5] = q0; v[6] = pa0; v[7] = 2.0;
             break;
         case ORC_GAUSSIAN:
             v[0] = xc; v[1] = yc; v[2] = pk; v[3] = r0; v[4] = q0; v[5] = pa0;

@@ -18,8 +18,8 @@ enum { ORC_ST_CONVERGED = 0, ORC_ST_MAXITER = 1, ORC_ST_STALLED = 2, ORC_ST_NONF
 /* One component.  Natural slots per type (PA in degrees):
  *   SERSIC   x0 y0 mag r_e n q pa box    (box: B of eq. (r); 0 = ellipse)
  *   EXPDISK  x0 y0 mag r_s q pa
- *   FERRER   x0 y0 mag r_out q pa a b          (a, b always fixed)
- *   KING     x0 y0 I0 r_c r_t q pa alpha       (alpha always fixed)
+ *   FERRER   x0 y0 mag r_out q pa a b          (a, b fixed or free)
+ *   KING     x0 y0 I0 r_c r_t q pa alpha       (alpha fixed or free)
  *   GAUSSIAN x0 y0 I0 fwhm q pa
  *   MOFFAT   x0 y0 mag fwhm q pa beta          (beta always fixed)
  *   SKY      sky

@@ -10,13 +10,14 @@ def from_spec(name: str, oversample: int = 10, os_window: int = 5) -> O.Model:
 
 
 def single(type_: int, convolve: bool = True, fixed=None, sky: bool = False, oversample: int = 10,
-           free=None, box: bool = False) -> O.Model:
-    """One component with every slot free (except shape constants, and the
-    Sersic boxiness unless `box`), plus an optional sky column at the end."""
+           free=None, box: bool = False, shape: bool = False) -> O.Model:
+    """One component with every slot free (except shape constants -- Ferrer a,
+    b and King alpha are free with `shape` -- and the Sersic boxiness unless
+    `box`), plus an optional sky column at the end."""
     slots = O.SLOTS[type_]
     idx, fx, k = [], [], 0
     for s, name in enumerate(slots):
-        if (name in ("a", "b", "alpha", "beta") or (name == "box" and not box)
+        if ((name in ("a", "b", "alpha") and not shape) or name == "beta" or (name == "box" and not box)
                 or (free is not None and name not in free)):
             idx.append(-1)
             fx.append((fixed or {}).get(name, 0.0))

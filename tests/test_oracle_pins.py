@@ -339,6 +339,8 @@ CASES = {
     "moffat_point": (single(O.MOFFAT, convolve=False, fixed={"beta": 3.0}, sky=True),
                      [10.55, 10.45, 17.0, 2.5, 0.8, 50.0, 1.0]),
     "sersic_tilt": (from_spec("sersic_tilt"), [10.52, 10.47, 18.0, 3.0, 1.5, 0.6, 30.0, 2.0, 0.03, -0.05]),
+    "ferrer_free_shape": (single(O.FERRER, sky=True, shape=True), [10.55, 10.45, 18.0, 6.3, 0.45, 60.0, 3.0, 0.5, 1.0]),
+    "king_free_alpha": (single(O.KING, sky=True, shape=True), [10.55, 10.45, 30.0, 1.7, 9.3, 0.8, 20.0, 2.5, 1.0]),
     "sersic_boxy": (single(O.SERSIC, sky=True, box=True), [10.52, 10.47, 18.0, 3.0, 1.5, 0.6, 30.0, 0.6, 2.0]),
     # with c = B + 2 < 2 the profile has |Y|^(c-1) behaviour across the component's axes, where
     # differences are meaningless: PA 58 deg keeps every pixel centre 0.014 px or more off them

@@ -498,19 +498,36 @@ def mixed_main(args, n: int, seed: int, chunks):
         outs.append(o)
 
     def step(ev):
-        if ev:
-            ev[0].record()
-        for (kind, b, gm, db), o in zip(batches, outs):
+        for j, ((kind, b, gm, db), o) in enumerate(zip(batches, outs)):
+            if ev:
+                ev[j][0].record()
             if kind == "sersic":
                 G.gm_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter, ctx=ctx, out=o)
             else:
                 guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
                 G.gm_fit_batch(gm, db, guess, ctx=ctx, out=o[:4])
-        if ev:
-            ev[1].record()
+            if ev:
+                ev[j][1].record()
 
-    wall, evs = timed(step, args.steps, args.warmup, "mixed")
-    ms = float(np.mean([evs[i][0].elapsed_time(evs[i][1]) for i in range(args.steps)]))
+    # a step takes tens of seconds: each is synchronised and logged (the wait
+    # for the device is inside the timed region, as at its end)
+    for i in range(args.warmup):
+        step(None)
+        torch.cuda.synchronize()
+        log(f"mixed: warmup step {i + 1}/{args.warmup} done")
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in batches] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+        torch.cuda.synchronize()
+        log(f"mixed: timed step {i + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)")
+    wall = time.perf_counter() - t0
+    ms = float(np.mean([sum(e[0].elapsed_time(e[1]) for e in evs[i]) for i in range(args.steps)]))
+    kind_ms = {}
+    for j, (kind, b, gm, db) in enumerate(batches):
+        kind_ms[kind] = kind_ms.get(kind, 0.0) + float(np.mean([evs[i][j][0].elapsed_time(evs[i][j][1])
+                                                                  for i in range(args.steps)]))
     per_kind = {}
     for (kind, b, gm, db), o in zip(batches, outs):
         st = o[3].cpu().numpy()
@@ -520,9 +537,11 @@ def mixed_main(args, n: int, seed: int, chunks):
         d["iters"] += float(o[2].cpu().numpy().sum())
         if kind == "sersic":
             d["fallback"] += int((o[4].cpu().numpy() != 0).sum())
-    for d in per_kind.values():
+    for kind, d in per_kind.items():
         d["converged_frac"] = d["converged"] / max(d["n"], 1)
         d["mean_iters"] = d["iters"] / max(d["n"], 1)
+        d["ms_per_step"] = kind_ms[kind]
+        d["galaxies_per_s"] = d["n"] / (kind_ms[kind] / 1e3)
         del d["iters"]
     cpu = parity = None
     if args.cpu_sample != 0:

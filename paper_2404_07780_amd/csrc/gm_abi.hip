@@ -285,14 +285,21 @@ int max_k(const CallInfo &ci)
 namespace {
 
 // Natural slots per profile type (index = type), the LM slots among them in
-// the plain families, and the first shape constant (trailing slots that stay
-// fixed).  The Sersic's eighth slot, the boxiness B of eq. (r), is no shape
-// constant: a Sersic with B free or not 0 runs in the boxy family.
+// the plain families, and the first slot that is always fixed (Moffat beta).
+// The Sersic's eighth slot, the boxiness B of eq. (r), runs in the boxy
+// family when free or not 0; the shape exponents Ferrer a, b and King alpha
+// are fixed constants of the plain families and, when any is a column, LM
+// variables of the free-shape families.
 const int kSlots[9] = {0, 8, 6, 8, 8, 6, 7, 1, 3};
 const int kLmSlots[9] = {0, 7, 6, 6, 7, 6, 6, 1, 3};
-const int kShape0[9] = {0, 8, 6, 6, 7, 6, 6, 1, 3};
+const int kShape0[9] = {0, 8, 6, 8, 8, 6, 6, 1, 3};
 
 bool boxy(const gm_component &c) { return c.type == GM_SERSIC && (c.param_index[7] >= 0 || c.fixed[7] != 0.0); }
+bool free_shape(const gm_component &c)
+{
+    return (c.type == GM_FERRER && (c.param_index[6] >= 0 || c.param_index[7] >= 0)) ||
+           (c.type == GM_KING && c.param_index[7] >= 0);
+}
 
 bool comp_ok(const gm_component &c, int p)
 {
@@ -318,7 +325,7 @@ void take(const gm_component &c, int s, int k, ModelArgs &ma)
 // Family tables (variants in order of preference), built once.
 enum {
     FAM_SERSIC = 1, FAM_EXPDISK, FAM_FERRER, FAM_KING, FAM_GAUSSIAN, FAM_MOFFAT, FAM_BULGEDISK, FAM_SERSICBAR,
-    FAM_SERSICTILT, FAM_SERSICBOX
+    FAM_SERSICTILT, FAM_SERSICBOX, FAM_FERRERFREE, FAM_KINGFREE
 };
 
 FamilyOps family(int id, Variant a, Variant b)
@@ -355,9 +362,11 @@ const FamilyOps *family_table(int id)
         family(FAM_SERSICBAR, var_sersicbar_2(), var_sersicbar_3()),
         family(FAM_SERSICTILT, var_sersictilt_1(), var_sersictilt_2()),
         family(FAM_SERSICBOX, var_sersicbox_1(), var_sersicbox_2()),
+        family(FAM_FERRERFREE, var_ferrerfree_1(), var_ferrerfree_2()),
+        family(FAM_KINGFREE, var_kingfree_1(), var_kingfree_2()),
     };
     // indexed by id: the entries are in FAM_* order
-    static_assert(sizeof(tab) / sizeof(tab[0]) == FAM_SERSICBOX, "family table out of order");
+    static_assert(sizeof(tab) / sizeof(tab[0]) == FAM_KINGFREE, "family table out of order");
     return &tab[id - 1];
 }
 
@@ -426,16 +435,16 @@ int match_model(const gm_model *m, Match &out)
     if (nrad == 1) {
         const gm_component &c = *rad[0];
         convolved = c.convolve != 0;
-        const bool bx = boxy(c);
-        int ns = bx ? 8 : kLmSlots[c.type];
+        const bool bx = boxy(c), fs = free_shape(c);
+        int ns = (bx || fs) ? 8 : kLmSlots[c.type];
         for (int s = 0; s < ns; ++s) take(c, s, s, ma);
         for (int s = ns; s < kSlots[c.type]; ++s) ma.cst[s - ns] = c.fixed[s];
-        if (bx) {
-            // the boxy Sersic is compiled with a flat sky
+        if (bx || fs) {
+            // the boxy Sersic and the free-shape Ferrer and King are compiled with a flat sky
             if (sky && sky->type == GM_SKYPLANE) return GM_EUNSUPPORTED;
             if (sky) take(*sky, 0, ns, ma);
             nint = ns + 1;
-            ops = family_table(FAM_SERSICBOX);
+            ops = family_table(bx ? FAM_SERSICBOX : c.type == GM_FERRER ? FAM_FERRERFREE : FAM_KINGFREE);
         } else if (sky && sky->type == GM_SKYPLANE) {
             // the tilted-plane sky is compiled for a single Sersic
             if (c.type != GM_SERSIC) return GM_EUNSUPPORTED;
@@ -451,7 +460,7 @@ int match_model(const gm_model *m, Match &out)
         // Sersic + (exponential disk | Ferrer) with a shared centre, both convolved
         const gm_component *a = rad[0], *b = rad[1];
         if (sky && sky->type == GM_SKYPLANE) return GM_EUNSUPPORTED;
-        if (boxy(*a) || boxy(*b)) return GM_EUNSUPPORTED;
+        if (boxy(*a) || boxy(*b) || free_shape(*a) || free_shape(*b)) return GM_EUNSUPPORTED;
         if (b->type == GM_SERSIC) std::swap(a, b);
         if (a->type != GM_SERSIC || !(b->type == GM_EXPDISK || b->type == GM_FERRER) || !a->convolve ||
             !b->convolve)

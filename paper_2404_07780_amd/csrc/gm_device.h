@@ -20,24 +20,28 @@ constexpr float kDMag = -0.921034037197618f;   // d ln F / d m = -0.4 ln 10
 // Kinds of LM variables: centres, magnitudes, amplitudes, axis ratio and sky
 // are used as they are; positive scales and the Sersic index through their
 // natural log; position angles in radians (degrees at the interface).
-enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY, KSKYG, KBOX };
+// Ferrer a and King alpha (positive exponents) go through their log, Ferrer b
+// and the boxiness as they are.
+enum Kind : int { KX0 = 1, KY0, KMAG, KAMP, KSCALE, KN, KQ, KPA, KSKY, KSKYG, KBOX, KFA, KFB, KKAL };
+
+__host__ __device__ inline bool log_kind(int kind) { return kind == KSCALE || kind == KN || kind == KFA || kind == KKAL; }
 
 __host__ __device__ inline double nat_to_u(int kind, double p)
 {
-    if (kind == KSCALE || kind == KN) return log(p);
+    if (log_kind(kind)) return log(p);
     if (kind == KPA) return p * (kPi / 180.0);
     return p;
 }
 __host__ __device__ inline double u_to_nat(int kind, double u)
 {
-    if (kind == KSCALE || kind == KN) return exp(u);
+    if (log_kind(kind)) return exp(u);
     if (kind == KPA) return u * (180.0 / kPi);
     return u;
 }
 // d(natural) / d(u)
 __host__ __device__ inline double dnat_du(int kind, double p)
 {
-    if (kind == KSCALE || kind == KN) return p;
+    if (log_kind(kind)) return p;
     if (kind == KPA) return 180.0 / kPi;
     return 1.0;
 }
@@ -711,6 +715,157 @@ struct King {
     }
 };
 
+// Ferrer with free shape exponents (Sec. 4.2.2): slots x0 y0 mag ln r_out q
+// theta ln a b.  With u = (r / r_out)^(2-b) and c2 = 1 + 2 / (2 - b):
+//   d ln I / d a = ln(1 - u) - 1/a - (psi(a) - psi(a + c2)),
+//   d ln I / d b = a (u / (1 - u)) ln(r / r_out) - 2 (psi(c2) - psi(a + c2)) / (2 - b)^2,
+// the psi terms from I0 = F / (pi q r_out^2 a beta(a, c2)).
+struct FerrerFree {
+    struct K : Ferrer::K {
+        float dlaf, dlbf;
+    };
+    static constexpr int NS = 8, IQ = 4, ITH = 5, IS0 = 3, IS1 = -1;
+    __host__ __device__ static constexpr int kind(int s) { return s == 6 ? KFA : s == 7 ? KFB : Ferrer::kind(s); }
+    __device__ static void prep(const double *u, const double *, double m0, int H, int W, int osf, int osw, int lane,
+                                K &k)
+    {
+        const double a = exp(u[6]), bb = u[7], c2 = 1.0 + 2.0 / (2.0 - bb);
+        const double shape[2] = {a, bb};
+        Ferrer::prep(u, shape, m0, H, W, osf, osw, lane, k);
+        k.dlaf = (float)(-1.0 / a - (digamma(a) - digamma(a + c2)));
+        k.dlbf = (float)(-2.0 * (digamma(c2) - digamma(a + c2)) / ((2.0 - bb) * (2.0 - bb)));
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float I, u, omu, lnuf, lomu;
+        if constexpr (F64) {
+            double lnu = k.e2 * (log(p.r2) - k.lnro2);     // ln (r/r_out)^(2-b)
+            if (lnu >= 0.0) {
+                I64 = 0.0;
+                for (int s = 0; s < NS; ++s) d[s] = 0.0f;
+                return;
+            }
+            double omud = -expm1(lnu), lo = log(omud);
+            I64 = exp(k.lnI0 + k.a * lo);
+            I = (float)I64;
+            u = (float)exp(lnu);
+            omu = (float)omud;
+            lnuf = (float)lnu;
+            lomu = (float)lo;
+        } else {
+            lnuf = 0.5f * k.ef * __logf(p.r2f * k.iro2f);
+            if (lnuf >= 0.0f) {
+                I64 = 0.0;
+                for (int s = 0; s < NS; ++s) d[s] = 0.0f;
+                return;
+            }
+            omu = -expm1f(lnuf);
+            u = 1.0f - omu;
+            lomu = __logf(omu);
+            I = __expf((float)k.lnI0 + k.af * lomu);
+            I64 = I;
+        }
+        const float iomu = frcp(omu);
+        float dl = -k.af * k.ef * u * frcp(2.0f * p.r2f * omu);   // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, -k.g.iqf, gd);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = kDMag * I;
+        d[3] = I * (-2.0f + k.af * k.ef * u * iomu);
+        d[4] = gd[2];
+        d[5] = gd[3];
+        d[6] = I * k.af * (lomu + k.dlaf);
+        d[7] = I * (k.af * u * iomu * lnuf * frcp(k.ef) + k.dlbf);
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double pk, int nrad,
+                                 double *v)
+    {
+        Ferrer::guess(xc, yc, m, r0, q0, pa0, pk, nrad, v);
+        v[6] = 0.5;     // the values printed in Appendix C
+        v[7] = 1.9;
+    }
+};
+
+// King with a free alpha (Sec. 4.2.3): slots x0 y0 I0 ln r_c ln r_t q theta
+// ln alpha.  With ln(I / I0) = alpha [ln(S - A) - ln(1 - A)], S = s^(-1/alpha),
+// A = T^(-1/alpha), T = 1 + r_t^2 / r_c^2:
+//   d I / d ln alpha = I (alpha ln((S - A)/(1 - A)) + (S ln s - A ln T)/(S - A) + A ln T/(1 - A)).
+struct KingFree {
+    struct K : King::K {
+        float lnTf;
+    };
+    static constexpr int NS = 8, IQ = 5, ITH = 6, IS0 = 3, IS1 = 4;
+    __host__ __device__ static constexpr int kind(int s) { return s == 7 ? KKAL : King::kind(s); }
+    __device__ static void prep(const double *u, const double *, double m0, int H, int W, int osf, int osw, int lane,
+                                K &k)
+    {
+        const double al[1] = {exp(u[7])};
+        King::prep(u, al, m0, H, W, osf, osw, lane, k);
+        k.lnTf = (float)log(1.0 + exp(2.0 * (u[4] - u[3])));
+    }
+    template <bool F64>
+    __device__ static void pt(const K &k, double dx, double dy, double &I64, float *d)
+    {
+        Pt<F64> p = frame<F64>(k.g, dx, dy);
+        float shape, s, S, D, lns, lDA;
+        if constexpr (F64) {
+            if (p.r2 >= k.rt2) {
+                I64 = 0.0;
+                for (int q = 0; q < NS; ++q) d[q] = 0.0f;
+                return;
+            }
+            double sd = 1.0 + p.r2 * k.irc2, ls = log(sd);
+            double Sd = exp(-k.ial * ls);
+            double Dd = Sd - k.A;
+            double lr = log(Dd / (1.0 - k.A));
+            double shd = exp(k.al * lr);
+            I64 = k.I0 * shd;
+            shape = (float)shd;
+            s = (float)sd;
+            S = (float)Sd;
+            D = (float)Dd;
+            lns = (float)ls;
+            lDA = (float)lr;
+        } else {
+            if (p.r2f >= k.rt2f) {
+                I64 = 0.0;
+                for (int q = 0; q < NS; ++q) d[q] = 0.0f;
+                return;
+            }
+            s = 1.0f + p.r2f * k.irc2f;
+            lns = __logf(s);
+            S = __expf(-k.ialf * lns);
+            D = S - k.Af;
+            lDA = __logf(D / (1.0f - k.Af));
+            shape = __expf(k.alf * lDA);
+            I64 = k.I0f * shape;
+        }
+        float I = k.I0f * shape;
+        float iD = frcp(D), iomA = frcp(1.0f - k.Af);
+        float dl = -S * k.irc2f * frcp(s) * iD;              // d ln I / d r^2
+        float gd[4];
+        geometry_derivs<F64>(k.g, p, I, dl, 0.0f, gd);
+        float dS_rc = 2.0f * S * (s - 1.0f) * k.ialf * frcp(s);
+        d[0] = gd[0];
+        d[1] = gd[1];
+        d[2] = shape;
+        d[3] = I * k.alf * (k.dA_rcf * iomA + (dS_rc - k.dA_rcf) * iD);
+        d[4] = I * k.alf * (-k.dA_rcf * iomA + k.dA_rcf * iD);
+        d[5] = gd[2];
+        d[6] = gd[3];
+        d[7] = I * (k.alf * lDA + (S * lns - k.Af * k.lnTf) * iD + k.Af * k.lnTf * iomA);
+    }
+    __device__ static void guess(double xc, double yc, double m, double r0, double q0, double pa0, double pk, int nrad,
+                                 double *v)
+    {
+        King::guess(xc, yc, m, r0, q0, pa0, pk, nrad, v);
+        v[7] = 2.0;
+    }
+};
+
 // Gaussian (Sec. 4.2.4): I = I0 exp(-r^2 / (2 sigma^2)), FWHM = 2 sqrt(2 ln 2) sigma.
 // Slots x0 y0 I0 ln fwhm q theta.
 struct Gaussian {
@@ -978,6 +1133,8 @@ struct FamPair {
 using FamSersic = FamSingle<Sersic>;
 using FamSersicTilt = FamSingle<Sersic, true>;
 using FamSersicBox = FamSingle<SersicBox>;
+using FamFerrerFree = FamSingle<FerrerFree>;
+using FamKingFree = FamSingle<KingFree>;
 using FamBulgeDisk = FamPair<Sersic, ExpDisk>;
 using FamSersicBar = FamPair<Sersic, Ferrer>;
 

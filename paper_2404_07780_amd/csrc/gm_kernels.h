@@ -908,6 +908,9 @@ __device__ inline double clamp_var(int k, double v, int H, int W)
     case KN: return fmin(fmax(v, log(0.2)), log(10.0));
     case KQ: return fmin(fmax(v, 0.05), 20.0);
     case KBOX: return fmin(fmax(v, -0.9), 2.0);
+    case KFA: return fmin(fmax(v, log(0.1)), log(10.0));
+    case KFB: return fmin(fmax(v, -1.0), 1.95);
+    case KKAL: return fmin(fmax(v, log(0.5)), log(10.0));
     default: return v;
     }
 }

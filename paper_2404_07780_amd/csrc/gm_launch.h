@@ -421,6 +421,10 @@ Variant var_sersictilt_1();
 Variant var_sersictilt_2();
 Variant var_sersicbox_1();
 Variant var_sersicbox_2();
+Variant var_ferrerfree_1();
+Variant var_ferrerfree_2();
+Variant var_kingfree_1();
+Variant var_kingfree_2();
 
 // A caller's gm_model matched against the compiled families (gm_abi.hip).
 struct Match {

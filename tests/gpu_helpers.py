@@ -44,7 +44,7 @@ def image_parity(gpu: np.ndarray, ref: np.ndarray, rel: float = 1e-5, floor: flo
 
 # floors of the parameter parity metric per parameter kind (natural units)
 FLOORS = {"x0": 1.0, "y0": 1.0, "re": 0.1, "rs": 0.1, "rout": 0.1, "rc": 0.1, "rt": 0.1, "fwhm": 0.1, "n": 0.1,
-          "q": 0.01}
+          "q": 0.01, "box": 0.1, "a": 0.1, "b": 0.1, "alpha": 0.1}
 
 
 def param_parity(names, gpu, ref, sky_sigma: float = 1.0, rel: float = 1e-4):

@@ -111,3 +111,35 @@ def test_adam_reaches_lm_minimum_on_gpu():
     print(f"adam vs LM chi2: median rel excess {np.median(rel):.3g}, max {rel.max():.3g}", flush=True)
     assert rel.min() > -1e-6
     assert np.median(rel) < 1e-5
+
+
+@pytest.mark.parametrize("kind", ["point", "king", "sersicbar"])
+def test_adam_parity_masked_mixed(kind):
+    """Masked galaxies of the mixed workload: unconvolved point sources (the
+    unit PSF, its own flip), King and Sersic + bar, 12 steps.  The bar's
+    derivative images (a = 0.5) have an integrable singularity at r_out where
+    FP32 values hold ~1e-3 of the column maximum (the Jacobian parity bar for
+    those columns is 2e-3); its four parameters are held to 2e-3, the rest to
+    1e-4."""
+    from tests.gpu_helpers import oracle_mixed
+
+    print(f"adam parity mixed {kind}", flush=True)
+    b = oracle_mixed(60, seed=44)[kind]
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    names = S.MODEL_SPECS[b.model]["names"]
+    start, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, omega=b.omega)
+    gp, gc, gs = [t.cpu().numpy() for t in G.gm_fit_adam(gm, _dev(b), start, steps=12)]
+    rp, rc, rs = O.fit_adam_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, start,
+                                  omega=b.omega, steps=12)
+    assert np.array_equal(gs, rs)
+    bar = np.array([nm in ("mag_bar", "rout", "q_bar", "pa_bar") for nm in names])
+    worst = 0.0
+    for g in range(b.n):
+        sky_sig = float(np.median(b.image(b.sigma, g)))
+        ok, w = param_parity(names, gp[g], rp[g], sky_sigma=sky_sig)
+        okb, wb = param_parity(names, gp[g], rp[g], sky_sigma=sky_sig, rel=2e-3)
+        ok = np.where(bar, okb, ok)
+        worst = max(worst, float(np.max(np.where(bar, wb, w))))
+        assert ok.all(), (g, w, wb)
+    print(f"  {b.n} galaxies within their bars; worst ratio {worst:.3g}", flush=True)

@@ -99,6 +99,14 @@ WORKLOADS = {
                 desc="8192 boxy and discy single-Sersic galaxies (boxiness B ~ U(-0.5, 1) of the generalised "
                      "radius), 64x64, Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise; LM with B free from "
                      "the moment start (B = 0)"),
+    "kingfree": dict(n=8192, cfg="sersic64", seed=0, shape="king_free",
+                     desc="8192 single-King galaxies with alpha U(1.5, 3) (r_c = r_e/2 and r_t = U(6, 16) r_c of the "
+                          "single-Sersic draw), 64x64, Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise; LM with "
+                          "alpha free from the moment start (alpha = 2)"),
+    "ferrerfree": dict(n=8192, cfg="sersic64", seed=0, shape="ferrer_free",
+                       desc="8192 single-Ferrer galaxies with a U(1, 3), b U(0, 1.5) (r_out = 2 r_e of the "
+                            "single-Sersic draw), 64x64, Gaussian PSF FWHM 1.5 px on 15x15, unit-sigma noise; LM "
+                            "with a and b free from the moment start (a = 0.5, b = 1.9)"),
     "bulgedisk": dict(n=8192, cfg="bulgedisk", seed=0,
                       desc="8192 Sersic bulge + exponential disk galaxies (shared centre), 128x128, Moffat PSF "
                            "25x25, Poisson + read noise, LM from moment-based start"),
@@ -109,7 +117,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_batch(cfg: str, n: int, seed: int, box: bool = False):
+def make_batch(cfg: str, n: int, seed: int, box: bool = False, shape: str = None):
     """Draw, render at unit flux with the HIP forward model, add noise: on the
     device (Philox) for the unit-sigma workload, on the host otherwise.  With
     box the Sersics get a boxiness B ~ U(-0.5, 1) (model sersic_box)."""
@@ -118,6 +126,8 @@ def make_batch(cfg: str, n: int, seed: int, box: bool = False):
         B = np.random.default_rng(seed + 1000).uniform(-0.5, 1.0, b.n)
         b.truth = np.concatenate([b.truth[:, :7], B[:, None], b.truth[:, 7:]], axis=1)
         b.model = "sersic_box"
+    if shape:
+        S.free_shape_variant(b, shape)
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
     unused = torch.empty(b.npix, dtype=torch.float32, device="cuda")
     db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, unused, unused, b.psf)
@@ -145,17 +155,23 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
     return 2.0 * hw * k2 * npl, 2.0 * hw * (p * (p + 1) / 2 + p + 1)
 
 
-def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20, box: bool = False):
+def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20, box: bool = False,
+                 shape: str = None):
     """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
     noised on the host), all host cores, LM from its own moment start; the GPU
     fits of the same data (plain, and learned when a network is given) are
     judged against it."""
     import oracle as O
-    from tests.gpu_helpers import oracle_batch, oracle_box_batch, param_parity
+    from tests.gpu_helpers import oracle_batch, oracle_box_batch, oracle_shape_batch, param_parity
     from tests.oracle_models import from_spec
 
     ncores = len(os.sched_getaffinity(0))
-    b = oracle_box_batch(cfg, n_sample, seed=seed) if box else oracle_batch(cfg, n_sample, seed=seed)
+    if box:
+        b = oracle_box_batch(cfg, n_sample, seed=seed)
+    elif shape:
+        b = oracle_shape_batch(cfg, n_sample, shape, seed=seed)
+    else:
+        b = oracle_batch(cfg, n_sample, seed=seed)
     om = from_spec(b.model)
     db = G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf)
     t0 = time.perf_counter()
@@ -723,11 +739,12 @@ def main():
         return mixed_main(args, n, seed, mixed_chunks)
     learned = args.workload == "learned"
     if args.cpu_sample is None:
-        args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32, "box": 256}.get(args.workload, 160)
+        args.cpu_sample = {"learned": 2048, "sersic64": 64, "paper": 32, "box": 256, "kingfree": 256,
+                           "ferrerfree": 256}.get(args.workload, 160)
     mlp, train_info = (train_network(args.train_n, args.epochs, args.train_batch) if learned else (None, None))
 
     t0 = time.perf_counter()
-    b, gm, db = make_batch(wl["cfg"], n, seed, box=wl.get("box", False))
+    b, gm, db = make_batch(wl["cfg"], n, seed, box=wl.get("box", False), shape=wl.get("shape"))
     torch.cuda.synchronize()
     log(f"generated {n} galaxies ({b.npix / 1e6:.1f} Mpx) in {time.perf_counter() - t0:.1f} s")
     from paper_2404_07780_amd import tune
@@ -830,7 +847,7 @@ def main():
     if args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} galaxies")
         cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp, args.proposal_max_iter,
-                                   box=wl.get("box", False))
+                                   box=wl.get("box", False), shape=wl.get("shape"))
 
     key = f"{args.workload}:{n}:{seed}:{source_hash()}"
     out = {

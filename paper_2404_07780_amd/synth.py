@@ -67,6 +67,24 @@ MODEL_SPECS: Dict[str, dict] = {
         ],
         names=["x0", "y0", "mag", "re", "n", "q", "pa", "box", "sky"],
     ),
+    # single King with alpha free (Sec. 4.2.3) + sky: x0 y0 I0 rc rt q pa alpha sky
+    "king_free": dict(
+        p=9,
+        comps=[
+            (KING, 1, [0, 1, 2, 3, 4, 5, 6, 7], []),
+            (SKY, 0, [8], []),
+        ],
+        names=["x0", "y0", "I0", "rc", "rt", "q", "pa", "alpha", "sky"],
+    ),
+    # single Ferrer with a and b free (Sec. 4.2.2) + sky: x0 y0 mag rout q pa a b sky
+    "ferrer_free": dict(
+        p=9,
+        comps=[
+            (FERRER, 1, [0, 1, 2, 3, 4, 5, 6, 7], []),
+            (SKY, 0, [8], []),
+        ],
+        names=["x0", "y0", "mag", "rout", "q", "pa", "a", "b", "sky"],
+    ),
     # single Sersic + the tilted-plane sky of Appendix D: ... sky kx ky
     "sersic_tilt": dict(
         p=10,
@@ -121,6 +139,8 @@ FLUX_COLUMNS = {
     "sersic": [("mag", 2)],
     "sersic_tilt": [("mag", 2)],
     "sersic_box": [("mag", 2)],
+    "king_free": [("amp", 2)],
+    "ferrer_free": [("mag", 2)],
     "bulgedisk": [("mag", 2), ("mag", 7)],
     "sersicbar": [("mag", 2), ("mag", 7)],
     "king": [("amp", 2)],
@@ -222,6 +242,27 @@ def _sersic_draw(r: np.random.Generator, h: int, w: int):
     pa = r.uniform(0.0, 180.0)
     snr = math.exp(r.uniform(math.log(20.0), math.log(200.0)))
     return x0, y0, re, n, q, pa, snr
+
+
+def free_shape_variant(b: Batch, kind: str) -> Batch:
+    """Turn a drawn single-Sersic batch into single King ("king_free") or
+    Ferrer ("ferrer_free") galaxies with the same centres, axis ratios,
+    angles, SNRs and skies: King r_c = r_e / 2, r_t = U(6, 16) r_c, alpha
+    U(1.5, 3), unit amplitude; Ferrer r_out = 2 r_e, a U(1, 3), b U(0, 1.5),
+    unit flux.  Extra draws from the galaxy's own generator, stream 2."""
+    cfg = CONFIG_IDS[b.config]
+    t = np.zeros((b.n, 9))
+    for g in range(b.n):
+        r = _rng(b.seed, cfg, int(b.index[g]), 2)
+        x0, y0, _m, re, _n, q, pa, sky = b.truth[g]
+        if kind == "king_free":
+            rc = 0.5 * re
+            t[g] = [x0, y0, 1.0, rc, r.uniform(6.0, 16.0) * rc, q, pa, r.uniform(1.5, 3.0), sky]
+        else:
+            t[g] = [x0, y0, M0, 2.0 * re, q, pa, r.uniform(1.0, 3.0), r.uniform(0.0, 1.5), sky]
+    b.truth = t
+    b.model = kind
+    return b
 
 
 def draw(config: str, n: int, seed: int = 0, start: int = 0) -> Batch:

@@ -82,3 +82,15 @@ def oracle_box_batch(config: str, n: int, seed: int = 0, lo: float = -0.5, hi: f
     units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
                             for g in range(b.n)])
     return S.finish(b, units)
+
+
+def oracle_shape_batch(config: str, n: int, kind: str, seed: int = 0) -> S.Batch:
+    """Galaxies of `config` turned into King ("king_free") or Ferrer
+    ("ferrer_free") galaxies by synth.free_shape_variant, rendered by the
+    oracle and noised."""
+    b = S.free_shape_variant(S.draw(config, n, seed=seed), kind)
+    m = from_spec(b.model)
+    ut = S.unit_truth(b)
+    units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
+                            for g in range(b.n)])
+    return S.finish(b, units)

@@ -280,7 +280,12 @@ def bootstrap_main(args, n: int, seed: int):
 
     nb = args.n_boot
     b, gm, db = make_batch("sersic64", n, seed)
-    tune.apply(gm, db, sample=n, trials=0)
+    # the batch's own plain fits (1024 galaxies, ~15 ms each) are too few to rank schedules for
+    # the replica fits: one run picked a schedule 50% slower; the library default unless asked
+    sched = tune.apply(gm, db, sample=min(args.tune_sample, n), trials=0) if args.tune_sample > 0 else None
+    if sched:
+        log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']} "
+            f"({[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 2)) for t in sched['trials']]})")
     plan = G.gm_plan_fit(gm, db, errors=True)
     plan.launch()
     torch.cuda.synchronize()
@@ -314,7 +319,9 @@ def bootstrap_main(args, n: int, seed: int):
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"bootstrap: {WORKLOADS['bootstrap']['desc']}", "n_gal": n, "seed": seed,
-                   "n_boot": nb, "replica_fits_per_s": n * nb / (wall / args.steps)},
+                   "n_boot": nb, "replica_fits_per_s": n * nb / (wall / args.steps),
+                   "schedule": None if not sched else {"plane_groups": sched["plane_groups"],
+                                                       "wg_per_cu": sched["wg_per_cu"]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "lm_fit_kernel over the replicas (with the replication and reduction kernels)",

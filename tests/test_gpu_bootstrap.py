@@ -102,3 +102,36 @@ def test_bootstrap_rejects_bad_arguments():
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
     with pytest.raises(G.GmError):
         G.gm_bootstrap(gm, _dev(b), b.truth, n_boot=1)
+
+
+def test_bootstrap_replicas_masked():
+    """Masked galaxies (the mixed workload's Sersics): a replica's weight
+    multiplies Omega / sigma^2, so a masked pixel stays masked; the oracle
+    fits each replica with the mask and the replica's zero weights combined."""
+    from tests.gpu_helpers import oracle_mixed
+
+    b = oracle_mixed(12, seed=54)["sersic"]
+    om = from_spec(b.model)
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    names = S.MODEL_SPECS[b.model]["names"]
+    nb = 4
+    start = b.truth.copy()
+    err, rp, rs, _ = G.gm_bootstrap(gm, _dev(b), start, n_boot=nb, seed=SEED, want_replicas=True)
+    rp, rs = rp.cpu().numpy(), rs.cpu().numpy()
+    npass = nboth = 0
+    for g in range(b.n):
+        h, w = int(b.h[g]), int(b.w[g])
+        data, sigma = b.image(b.data, g), b.image(b.sigma, g)
+        mask = b.image(b.omega, g)
+        assert (mask == 0).mean() >= 0.05
+        for r in range(nb):
+            wt = philox_ref.replica_weights(SEED, g, r, h * w).reshape(h, w)
+            sig = np.where(wt > 0, sigma / np.sqrt(np.maximum(wt, 1)), sigma).astype(np.float32)
+            omega = ((wt > 0) & (mask != 0)).astype(np.uint8)
+            orp, _, _, ors = O.fit(om, data, sig, b.psf_of(g), start[g], omega=omega)
+            if ors == 0 and rs[g, r] == 0:
+                nboth += 1
+                ok, worst = param_parity(names, rp[g, r], orp, sky_sigma=float(np.median(sigma)))
+                npass += int(ok.all())
+    print(f"bootstrap replicas [masked]: {npass}/{nboth} within 1e-4 of the oracle", flush=True)
+    assert nboth >= 0.6 * b.n * nb and npass == nboth

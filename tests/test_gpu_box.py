@@ -96,3 +96,13 @@ def test_box_unsupported_combinations():
                              (S.EXPDISK, 1, [0, 1, 8, 9, 10, 11], []), (S.SKY, 0, [12], [])])
     with pytest.raises(G.GmError):
         G.gm_model_image(G.Model.from_spec(pair), db, np.zeros((2, 13)))
+
+
+def test_box_covariance_errors():
+    b = oracle_box_batch("sersic64", 4, seed=75)
+    om = from_spec("sersic_box")
+    gm = G.Model.from_spec(S.MODEL_SPECS["sersic_box"])
+    err = G.gm_param_errors(gm, _dev(b), b.truth).cpu().numpy()
+    for g in range(b.n):
+        ref = O.param_errors(om, b.image(b.data, g), b.image(b.sigma, g), b.psf_of(g), b.truth[g])
+        assert np.allclose(err[g], ref, rtol=1e-4, atol=0), (g, err[g], ref)

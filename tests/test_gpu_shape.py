@@ -96,3 +96,20 @@ def test_free_shape_fits(typ):
           f"oracle {np.mean(rs == 0):.2f}; fails {fails[:4]}", flush=True)
     assert np.mean(rs == 0) >= 0.6
     assert npass >= 0.9 * both.sum()
+
+
+@pytest.mark.parametrize("typ", [O.FERRER, O.KING])
+def test_free_shape_covariance_errors(typ):
+    om = single(typ, sky=True, shape=True)
+    gm = to_gm(om)
+    psf = S.moffat_psf(3.0, 2.0, 15)
+    params = np.array(CASES[typ])
+    rng = np.random.default_rng(85 + typ)
+    data = np.concatenate([(O.model_image(om, 80, 80, psf, params[g]) + rng.normal(size=(80, 80))).ravel()
+                           for g in range(2)]).astype(np.float32)
+    b = _batch([(80, 80)] * 2, psf, data=data)
+    err = G.gm_param_errors(gm, b, params).cpu().numpy()
+    for g in range(2):
+        ref = O.param_errors(om, data[g * 6400:(g + 1) * 6400].reshape(80, 80), np.ones((80, 80), np.float32), psf,
+                             params[g])
+        assert np.allclose(err[g], ref, rtol=1e-4, atol=0), (g, err[g], ref)

@@ -512,6 +512,21 @@ def mixed_main(args, n: int, seed: int, chunks):
             f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     ctx = G.context()
+    from paper_2404_07780_amd import tune
+
+    # one schedule per family (PSF side 25 throughout), tuned on the first chunk's batch of
+    # that family with a fixed number of trials per galaxy (throughput per evaluation)
+    scheds = {}
+    if args.tune_sample != 0:
+        for kind, b, gm, db in batches:
+            if kind in scheds:
+                continue
+            t0 = time.perf_counter()
+            r = tune.apply(gm, db, sample=min(4096, b.n), trials=4, ctx=ctx)
+            scheds[kind] = {"plane_groups": r["plane_groups"], "wg_per_cu": r["wg_per_cu"]}
+            log(f"mixed: {kind} schedule plane groups {r['plane_groups']}, workgroups/CU {r['wg_per_cu']} "
+                f"({[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 1)) for t in r['trials']]}, "
+                f"{time.perf_counter() - t0:.1f} s)")
     outs = []
     for kind, b, gm, db in batches:
         dev = db.device
@@ -577,7 +592,8 @@ def mixed_main(args, n: int, seed: int, chunks):
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"mixed: {WORKLOADS['mixed']['desc']}", "n_gal": n, "seed": seed,
-                   "chunk": MIXED_CHUNK, "batches": len(batches), "launch": "eager calls, library default schedules",
+                   "chunk": MIXED_CHUNK, "batches": len(batches), "launch": "eager calls",
+                   "schedules": scheds or "library defaults",
                    "proposal_max_iter": args.proposal_max_iter},
         "roofline": None,
         "gpu_ms_per_step": ms,

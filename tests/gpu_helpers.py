@@ -94,3 +94,73 @@ def oracle_shape_batch(config: str, n: int, kind: str, seed: int = 0) -> S.Batch
     units = np.concatenate([O.model_image(m, int(b.h[g]), int(b.w[g]), b.psf_of(g), ut[g]).ravel()
                             for g in range(b.n)])
     return S.finish(b, units)
+
+
+def judge_fit(om, names, data, sigma, psf, gp, rp, gc=None, rc=None, omega=None, step_tol: float = 1e-4):
+    """Judge the GPU's converged fit gp of one galaxy (data, sigma, omega: its
+    H x W images) against the oracle's converged fit rp of the same data.
+    Returns (ok, how, worst) with how one of
+
+    - "rel":   every parameter within the 1e-4 relative bar of param_parity;
+    - "sigma": every parameter within the 1e-4 relative bar or within
+               2 step_tol sigma_k of the oracle's, sigma_k the covariance error
+               at the oracle's fit.  The LM stops when the Gauss-Newton step is
+               below step_tol sigma_k in every variable, so each converged fit
+               lies within step_tol sigma_k of the minimum it converged to and
+               two fits of one minimum within 2 step_tol sigma_k of each other.
+               This is looser than the relative bar only for a parameter the
+               data determine to worse than half its value (sigma_k > |p_k| / 2,
+               e.g. the position angle of a nearly round galaxy, whose sigma is
+               tens of degrees);
+    - "hop":   the two centres lie on either side of an integer, so the
+               oversampled central window (rows floor(H - y0) +- 2, columns
+               floor(x0) +- 2) sits at different pixels at the two ends.  The
+               window placement makes chi^2 a piecewise smooth function of the
+               centre with a step where floor() changes, and each end is the
+               minimum of a different piece.  Both are results of the method:
+               the GPU's end must pass the oracle's own stop test (an oracle LM
+               started there converges without a trial), with chi^2 within 1
+               of the oracle's (statistically indistinguishable);
+    - "fail":  none of these.
+    """
+    sky = float(np.median(sigma))
+    ok, worst = param_parity(names, gp, rp, sky_sigma=sky)
+    if ok.all():
+        return True, "rel", float(worst.max())
+    err = O.param_errors(om, data, sigma, psf, rp, omega=omega)
+    d = np.array(gp, np.float64) - np.array(rp, np.float64)
+    for k, nm in enumerate(names):
+        if nm.startswith("pa"):
+            d[k] = (d[k] + 90.0) % 180.0 - 90.0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ds = np.abs(d) / (2.0 * step_tol * err)
+    sig_ok = ok | (np.isfinite(ds) & (ds <= 1.0))
+    if sig_ok.all():
+        return True, "sigma", float(np.max(np.where(ok, worst, ds)))
+    h = int(np.shape(data)[0])
+    ix, iy = names.index("x0"), names.index("y0")
+    hop = (math.floor(gp[ix]) != math.floor(rp[ix])) or (math.floor(h - gp[iy]) != math.floor(h - rp[iy]))
+    if hop and abs(d[ix]) < 1.0 and abs(d[iy]) < 1.0:
+        xp, xc, xn, xs = O.fit(om, data, sigma, psf, np.array(gp, np.float64), omega=omega, max_iter=1,
+                               step_tol=step_tol)
+        dchi = abs(gc - rc) if (gc is not None and rc is not None) else 0.0
+        if xs == 0 and xn == 0 and dchi <= 1.0:
+            return True, "hop", float(worst.max())
+    return False, "fail", float(worst.max())
+
+
+def judge_batch(b: S.Batch, om, names, gp, gc, gs, rp, rc, rs, step_tol: float = 1e-4):
+    """judge_fit over the galaxies both sides converged (status 0).  Returns
+    (npass, nboth, fails, counts): fails lists (galaxy, worst parameter's
+    ratio to the relative bar), counts the verdicts by kind."""
+    both = (np.asarray(gs) == 0) & (np.asarray(rs) == 0)
+    counts = {"rel": 0, "sigma": 0, "hop": 0, "fail": 0}
+    fails = []
+    for g in np.where(both)[0]:
+        omega = None if b.omega is None else b.image(b.omega, g)
+        ok, how, worst = judge_fit(om, names, b.image(b.data, g), b.image(b.sigma, g), b.psf_of(g), gp[g], rp[g],
+                                   gc[g], rc[g], omega=omega, step_tol=step_tol)
+        counts[how] += 1
+        if not ok:
+            fails.append((int(g), round(worst, 2)))
+    return int(both.sum()) - len(fails), int(both.sum()), fails, counts

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 import oracle as O
 from paper_2404_07780_amd import gmfit as G
 from paper_2404_07780_amd import synth as S
-from tests.gpu_helpers import image_parity, oracle_box_batch, param_parity
+from tests.gpu_helpers import image_parity, judge_batch, oracle_box_batch
 from tests.oracle_models import from_spec
 
 NAMES = S.MODEL_SPECS["sersic_box"]["names"]
@@ -72,18 +72,12 @@ def test_box_fit_parity(cfg, n):
     gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, gstart)]
     rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart)
     both = (gs == 0) & (rs == 0)
-    npass, fails = 0, []
-    for g in np.where(both)[0]:
-        ok, worst = param_parity(NAMES, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
-        if ok.all():
-            npass += 1
-        else:
-            fails.append((int(g), float(worst.max())))
+    npass, nboth, fails, counts = judge_batch(b, om, NAMES, gp, gc, gs, rp, rc, rs)
     err_b = np.abs(rp[both, 7] - b.truth[both, 7])
-    print(f"  {npass}/{int(both.sum())} within 1e-4; converged gpu {np.mean(gs == 0):.2f} oracle "
+    print(f"  {npass}/{nboth} pass {counts}; converged gpu {np.mean(gs == 0):.2f} oracle "
           f"{np.mean(rs == 0):.2f}; median |B - truth| {np.median(err_b):.3f}; fails {fails[:4]}", flush=True)
     assert np.mean(rs == 0) >= 0.75
-    assert npass >= 0.9 * both.sum()
+    assert npass == nboth
 
 
 def test_box_unsupported_combinations():

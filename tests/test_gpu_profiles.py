@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 import oracle as O
 from paper_2404_07780_amd import gmfit as G
 from paper_2404_07780_amd import synth as S
-from tests.gpu_helpers import image_parity, oracle_mixed, param_parity
+from tests.gpu_helpers import image_parity, judge_fit, oracle_mixed, param_parity
 from tests.oracle_models import from_spec, single, to_gm
 
 
@@ -111,6 +111,15 @@ def test_mixed_default_guess(mixed):
             assert np.allclose(mom[g], rm, rtol=1e-6, atol=1e-9), (kind, g)
 
 
+def _bar_vanished(names, p, sigma):
+    """The bar adds nothing to the model, so its flux and shape are not
+    identifiable: its r_out sits on the lower bound (0.1 px), where it covers
+    no sample point, or its total flux 10^(-0.4 (m - 22.5)) is below 1e-9 of
+    the pixel noise."""
+    flux = 10.0 ** (-0.4 * (p[names.index("mag_bar")] - 22.5))
+    return p[names.index("rout")] <= 0.1 + 1e-9 or flux <= 1e-9 * sigma
+
+
 @pytest.mark.parametrize("kind", ["sersic", "sersicbar", "king", "point"])
 def test_mixed_fit(mixed, kind):
     b = mixed[kind]
@@ -125,26 +134,28 @@ def test_mixed_fit(mixed, kind):
                                  omega=b.omega)
     names = S.MODEL_SPECS[b.model]["names"]
     both = (gs == 0) & (rs == 0)
-    npass, nalt, fails = 0, 0, []
+    npass, fails, counts = 0, [], {}
     for g in np.where(both)[0]:
-        ok, worst = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
-        if kind == "sersicbar" and rp[g, names.index("rout")] <= 0.1 + 1e-9:
-            # the bar collapsed onto the r_out bound: it covers no sample point, adds nothing to
-            # the model, and its flux and shape are not identifiable.  Compare the unique part
-            # (Sersic + sky) and require the GPU's bar to have collapsed as well.
+        sigma = b.image(b.sigma, g)
+        sig = float(np.median(sigma))
+        if kind == "sersicbar" and _bar_vanished(names, rp[g], sig):
+            # compare the identifiable part (Sersic + sky); the GPU's bar must have vanished too
             unique = [k for k, nm in enumerate(names) if nm not in ("mag_bar", "rout", "q_bar", "pa_bar")]
-            ok, worst = ok[unique], worst[unique]
-            ok = np.append(ok, gp[g, names.index("rout")] <= 0.1 + 1e-9)
-        if ok.all():
-            npass += 1
-        elif kind == "sersicbar" and gc[g] <= rc[g] * (1.0 + 1e-9):
-            # Sersic + bar is ill-conditioned (under a fifth of the fits from the moment start
-            # converge at all): two converged end points can differ; one with a chi^2 no worse
-            # than the oracle's is an equally valid fit
-            nalt += 1
+            ok, worst = param_parity([names[k] for k in unique], gp[g, unique], rp[g, unique], sky_sigma=sig)
+            ok, how = bool(ok.all()) and _bar_vanished(names, gp[g], sig), "vanished bar"
+            ok = ok and abs(gc[g] - rc[g]) <= 1e-6 * rc[g]
+            worst = float(worst.max())
         else:
-            fails.append((int(g), names[int(np.argmax(worst))], float(worst.max())))
-    print(f"mixed fit parity [{kind}]: {npass}/{int(both.sum())} pass ({nalt} valid alternatives) of {b.n}; gpu converged "
+            ok, how, worst = judge_fit(om, names, b.image(b.data, g), sigma, b.psf_of(g), gp[g], rp[g], gc[g], rc[g],
+                                       omega=b.image(b.omega, g))
+        counts[how] = counts.get(how, 0) + 1
+        if ok:
+            npass += 1
+        else:
+            fails.append((int(g), round(worst, 2)))
+            print(f"  fail g={g}: gpu {np.round(gp[g], 5).tolist()} chi2 {gc[g]:.9g} iters {gn[g]}\n"
+                  f"            orc {np.round(rp[g], 5).tolist()} chi2 {rc[g]:.9g} iters {rn[g]}", flush=True)
+    print(f"mixed fit parity [{kind}]: {npass}/{int(both.sum())} pass {counts} of {b.n}; gpu converged "
           f"{np.mean(gs == 0):.3f} oracle {np.mean(rs == 0):.3f}; iters gpu {gn.mean():.1f} oracle {rn.mean():.1f}; "
           f"fails {fails[:4]}", flush=True)
     if kind == "sersicbar":
@@ -153,4 +164,29 @@ def test_mixed_fit(mixed, kind):
         assert both.sum() >= 1
     else:
         assert both.sum() >= 0.7 * b.n
-    assert npass + nalt >= 0.9 * both.sum() and npass >= 0.5 * both.sum()
+    assert npass == both.sum()
+
+
+@pytest.mark.parametrize("trials", [1, 2])
+def test_sersic_bar_first_trials(mixed, trials):
+    """Sersic + bar from the oracle's moment start: the iterates after the
+    first LM trials agree with the oracle's within 1e-4 for every galaxy.  The
+    model is ill-conditioned (its r_out column is singular at the truncation),
+    so later iterates part as rounding differences grow; these trials pin the
+    step itself (damped solve, clamping, accept/reject) on all of them."""
+    b = mixed["sersicbar"]
+    om = from_spec(b.model)
+    gmod = to_gm(om)
+    names = S.MODEL_SPECS[b.model]["names"]
+    ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, omega=b.omega)
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gmod, _dev(b), ostart, max_iter=trials)]
+    rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart,
+                                 omega=b.omega, max_iter=trials)
+    assert np.array_equal(gs, rs) and np.array_equal(gn, rn)
+    worst = []
+    for g in range(b.n):
+        ok, w = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
+        worst.append(float(w.max()))
+        assert ok.all(), (g, names[int(np.argmax(w))], float(w.max()))
+    assert np.allclose(gc, rc, rtol=1e-4, atol=0)
+    print(f"bar after {trials} trials: worst ratio {max(worst):.3f} over {b.n} galaxies", flush=True)

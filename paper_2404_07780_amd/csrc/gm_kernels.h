@@ -646,23 +646,6 @@ __device__ void project_fixed(const int *freev, double *A, double *g)
 
 // Bounds of the LM variables (natural units: centres inside the cutout,
 // scales in [0.1, 2 max(H, W)] px, Sersic n in [0.2, 10], q in [0.05, 20]).
-template <class F>
-__device__ void clamp_u(double *u, int H, int W)
-{
-    const double big = 2.0 * (H > W ? H : W);
-    for (int k = 0; k < F::P; ++k) {
-        double lo = -INFINITY, hi = INFINITY;
-        switch (F::kind(k)) {
-        case KX0: lo = 0.0; hi = W; break;
-        case KY0: lo = 0.0; hi = H; break;
-        case KSCALE: lo = log(0.1); hi = log(big); break;
-        case KN: lo = log(0.2); hi = log(10.0); break;
-        case KQ: lo = 0.05; hi = 20.0; break;
-        default: break;
-        }
-        u[k] = fmin(fmax(u[k], lo), hi);
-    }
-}
 
 // Canonical form of every component: q > 1 -> (1/q, scale * q, theta + pi/2),
 // then theta wrapped into [0, pi).  u in internal layout; natural output.
@@ -897,22 +880,37 @@ __device__ inline void chol_inv_diag_rows(const double (&l)[P], double (&dg)[P])
     }
 }
 
+// v limited to [lo, hi] by comparisons: a NaN stays NaN (fmin/fmax would
+// replace it by a bound), so a non-finite start or step gives a non-finite
+// chi^2 and is never taken for a point inside the bounds.
+__device__ inline double clamp_to(double v, double lo, double hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Bounds of the LM variables (internal units: ln of scales, n and a, radians).
 template <class F>
 __device__ inline double clamp_var(int k, double v, int H, int W)
 {
     const double big = 2.0 * (H > W ? H : W);
     switch (F::kind(k)) {
-    case KX0: return fmin(fmax(v, 0.0), (double)W);
-    case KY0: return fmin(fmax(v, 0.0), (double)H);
-    case KSCALE: return fmin(fmax(v, log(0.1)), log(big));
-    case KN: return fmin(fmax(v, log(0.2)), log(10.0));
-    case KQ: return fmin(fmax(v, 0.05), 20.0);
-    case KBOX: return fmin(fmax(v, -0.9), 2.0);
-    case KFA: return fmin(fmax(v, log(0.1)), log(10.0));
-    case KFB: return fmin(fmax(v, -1.0), 1.95);
-    case KKAL: return fmin(fmax(v, log(0.5)), log(10.0));
+    case KX0: return clamp_to(v, 0.0, (double)W);
+    case KY0: return clamp_to(v, 0.0, (double)H);
+    case KSCALE: return clamp_to(v, log(0.1), log(big));
+    case KN: return clamp_to(v, log(0.2), log(10.0));
+    case KQ: return clamp_to(v, 0.05, 20.0);
+    case KBOX: return clamp_to(v, -0.9, 2.0);
+    case KFA: return clamp_to(v, log(0.1), log(10.0));
+    case KFB: return clamp_to(v, -1.0, 1.95);
+    case KKAL: return clamp_to(v, log(0.5), log(10.0));
     default: return v;
     }
+}
+
+template <class F>
+__device__ void clamp_u(double *u, int H, int W)
+{
+    for (int k = 0; k < F::P; ++k) u[k] = clamp_var<F>(k, u[k], H, W);
 }
 
 // Wave 0, all lanes: absorb the evaluation just made (the start point, or a

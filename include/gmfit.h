@@ -306,6 +306,30 @@ int gm_mlp_train_step(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t 
                       const int32_t *rows, const float *targets, int64_t step, const gm_adamw *opt,
                       double *loss_out, void *stream);
 
+/* One product of the dense layers' matrix-core kernels in FP32, without the
+ * layer epilogues (bias, GELU): C [m][n] (device FP32, pitch ldc >= n)
+ * = op(A) op(B) summed over k, from BF16 operands (device, every row
+ * 16-byte aligned, pitches multiples of 8):
+ *   GM_GEMM_NT  C = A B^T, A [m][lda >= k], B [n][ldb >= k], k a multiple
+ *               of 8: the forward product X W^T; a_rows (nullable, device
+ *               int32 [m]) takes row a_rows[i] of A as row i (the mini-batch
+ *               gather);
+ *   GM_GEMM_NN  C = A B,   A [m][lda >= k] (k a multiple of 8, a_rows as
+ *               for NT), B [k][ldb >= n] (n a multiple of 8): the backward
+ *               product dZ W;
+ *   GM_GEMM_TN  C = A^T B, A [k][lda >= m], B [k][ldb >= n] (m and n
+ *               multiples of 8); b_rows (nullable, device int32 [k]) takes
+ *               row b_rows[i] of B as row i: the weight gradient dZ^T X,
+ *               computed in K splits whose partial sums are added in a fixed
+ *               order (results do not depend on timing).
+ * Unused row maps must be NULL; GM_EINVAL otherwise and for sizes or
+ * pitches out of these rules.  Used by gm_mlp_forward, gm_mlp_backward and
+ * the tests of the products. */
+enum { GM_GEMM_NT = 0, GM_GEMM_NN = 1, GM_GEMM_TN = 2 };
+int gm_mlp_gemm(gm_ctx *ctx, int32_t op, int32_t m, int32_t n, int32_t k, const uint16_t *a, int64_t lda,
+                const int32_t *a_rows, const uint16_t *b, int64_t ldb, const int32_t *b_rows, float *c,
+                int64_t ldc, void *stream);
+
 /* Features of every galaxy: x_out [n_gal][ldx] BF16 (device, ldx >= 1056, a
  * multiple of 8); moments_out (device, nullable) [n_gal][8] =
  * {sky0, F0, x_c, y_c, m_g, r0, q0, theta0_rad}.  Any model (m0 is used). */

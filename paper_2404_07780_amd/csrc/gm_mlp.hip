@@ -31,6 +31,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // feature and target encoding (include/gmfit.h)
 constexpr int kInDim = 1056, kNOut = 7, kCells = 32;
@@ -86,38 +87,105 @@ struct GemmArgs {
     int64_t ldz;
 };
 
-// Stage rows r0..r0+63 x K slice k0..k0+31 of a K-contiguous operand
-// X(r, k) = P[map(r) * ld + k] into T[r][k]; zero outside R x K.
-__device__ inline void stage_kmajor(uint16_t *T, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
+// Staging of one 64 x 32 (rows x K) operand slice into an LDS tile
+// T[r][k] (pitch LDK), zero outside R x K, in two halves so that the global
+// reads of the next slice can be issued before the matrix-core work on the
+// current one: fetch (global -> registers), then put (registers -> LDS).
+//
+// K-contiguous operand X(r, k) = P[map(r) * ld + k]: each thread reads eight
+// consecutive K values of one row (16 bytes) and stores them with one
+// 16-byte LDS write.
+struct KMajorPiece {
+    u32x4 v;
+};
+
+__device__ inline void fetch_kmajor(KMajorPiece &f, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
                                     int k0, int K)
 {
     const int t = threadIdx.x;
     const int r = t >> 2, kc = (t & 3) * 8;
-    u32x4 v = {0u, 0u, 0u, 0u};
+    f.v = u32x4{0u, 0u, 0u, 0u};
     const int rr = r0 + r, k = k0 + kc;
     if (rr < R && k < K) {
         const int64_t row = map ? (int64_t)map[rr] : (int64_t)rr;
-        v = *reinterpret_cast<const u32x4 *>(P + row * ld + k);
+        f.v = *reinterpret_cast<const u32x4 *>(P + row * ld + k);
     }
-    *reinterpret_cast<u32x4 *>(T + r * LDK + kc) = v;
 }
 
-// Same tile of an R-contiguous operand X(r, k) = P[map(k) * ld + r].
-__device__ inline void stage_rmajor(uint16_t *T, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
+__device__ inline void put_kmajor(uint16_t *T, const KMajorPiece &f)
+{
+    const int t = threadIdx.x;
+    *reinterpret_cast<u32x4 *>(T + (t >> 2) * LDK + (t & 3) * 8) = f.v;
+}
+
+// R-contiguous operand X(r, k) = P[map(k) * ld + r]: each thread reads an
+// adjacent pair of rows (4 bytes) in four consecutive K rows and writes the
+// transposed values, four K values per row, as two 8-byte LDS stores (R is a
+// multiple of 8, so a pair is either inside R or outside it).
+struct RMajorPiece {
+    uint32_t v[4];
+};
+
+__device__ inline void fetch_rmajor(RMajorPiece &f, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
                                     int k0, int K)
 {
     const int t = threadIdx.x;
-    const int kr = t >> 3, rc = (t & 7) * 8;
-    u32x4 v = {0u, 0u, 0u, 0u};
-    const int k = k0 + kr, rr = r0 + rc;
-    if (k < K && rr < R) {
-        const int64_t row = map ? (int64_t)map[k] : (int64_t)k;
-        v = *reinterpret_cast<const u32x4 *>(P + row * ld + rr);
-    }
+    const int rp = 2 * (t & 31), kq = 4 * (t >> 5);
+    const int rr = r0 + rp;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) T[(rc + j) * LDK + kr] = (uint16_t)(v[j >> 1] >> (16 * (j & 1)));
+    for (int e = 0; e < 4; ++e) {
+        const int k = k0 + kq + e;
+        f.v[e] = 0u;
+        if (k < K && rr < R) {
+            const int64_t row = map ? (int64_t)map[k] : (int64_t)k;
+            f.v[e] = *reinterpret_cast<const uint32_t *>(P + row * ld + rr);
+        }
+    }
 }
 
+__device__ inline void put_rmajor(uint16_t *T, const RMajorPiece &f)
+{
+    const int t = threadIdx.x;
+    const int rp = 2 * (t & 31), kq = 4 * (t >> 5);
+    // row rp: the low halves of the four words; row rp + 1: the high halves
+    const u32x2 lo = {(f.v[0] & 0xffffu) | (f.v[1] << 16), (f.v[2] & 0xffffu) | (f.v[3] << 16)};
+    const u32x2 hi = {(f.v[0] >> 16) | (f.v[1] & 0xffff0000u), (f.v[2] >> 16) | (f.v[3] & 0xffff0000u)};
+    *reinterpret_cast<u32x2 *>(T + rp * LDK + kq) = lo;
+    *reinterpret_cast<u32x2 *>(T + (rp + 1) * LDK + kq) = hi;
+}
+
+template <bool RMAJOR>
+struct PieceOf {
+    typedef KMajorPiece type;
+};
+template <>
+struct PieceOf<true> {
+    typedef RMajorPiece type;
+};
+
+template <bool RMAJOR>
+__device__ inline void fetch(typename PieceOf<RMAJOR>::type &f, const uint16_t *P, int64_t ld, const int *map, int r0,
+                             int R, int k0, int K)
+{
+    if constexpr (RMAJOR)
+        fetch_rmajor(f, P, ld, map, r0, R, k0, K);
+    else
+        fetch_kmajor(f, P, ld, map, r0, R, k0, K);
+}
+
+template <bool RMAJOR>
+__device__ inline void put(uint16_t *T, const typename PieceOf<RMAJOR>::type &f)
+{
+    if constexpr (RMAJOR)
+        put_rmajor(T, f);
+    else
+        put_kmajor(T, f);
+}
+
+// C = A B over the K range [kbeg, kend) of this workgroup's split (blockIdx.z
+// of gridDim.z splits, each a whole number of K slices): the splits of an
+// EPI_F32 product write their partial sums to cf + z * M * ldcf, which
+// reduce_splits_kernel adds in split order.
 template <bool AT, bool BT, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 {
@@ -127,21 +195,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = 8 * (lane >> 4);
+    const int nsl = (g.K + GK - 1) / GK, per = (nsl + gridDim.z - 1) / gridDim.z;
+    const int kbeg = blockIdx.z * per * GK, kend = min(g.K, kbeg + per * GK);
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
-        if (AT)
-            stage_rmajor(As, g.a, g.lda, g.amap, m0, g.M, k0, g.K);
-        else
-            stage_kmajor(As, g.a, g.lda, g.amap, m0, g.M, k0, g.K);
-        if (BT)
-            stage_kmajor(Bs, g.b, g.ldb, nullptr, n0, g.N, k0, g.K);
-        else
-            stage_rmajor(Bs, g.b, g.ldb, g.bmap, n0, g.N, k0, g.K);
+    typename PieceOf<AT>::type fa;
+    typename PieceOf<!BT>::type fb;
+    if (kbeg < kend) {
+        fetch<AT>(fa, g.a, g.lda, g.amap, m0, g.M, kbeg, kend);
+        fetch<!BT>(fb, g.b, g.ldb, BT ? nullptr : g.bmap, n0, g.N, kbeg, kend);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        put<AT>(As, fa);
+        put<!BT>(Bs, fb);
         __syncthreads();
+        if (k0 + GK < kend) {       // the next slice's global reads overlap this slice's products
+            fetch<AT>(fa, g.a, g.lda, g.amap, m0, g.M, k0 + GK, kend);
+            fetch<!BT>(fb, g.b, g.ldb, BT ? nullptr : g.bmap, n0, g.N, k0 + GK, kend);
+        }
         bf16x8 af[2], bfr[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -156,6 +230,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
+    float *cf = g.cf;
+    if (EPI == EPI_F32) cf += (int64_t)blockIdx.z * g.M * g.ldcf;
     // lane holds C[4 (lane / 16) + r][lane % 16] of each 16 x 16 block
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -169,16 +245,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 const float v = acc[i][j][r];
                 if (EPI == EPI_GELU) {
                     const float zz = v + g.bias[n];
-                    if (g.cf) g.cf[(int64_t)m * g.ldcf + n] = zz;
+                    if (cf) cf[(int64_t)m * g.ldcf + n] = zz;
                     g.cb[(int64_t)m * g.ldcb + n] = f2bf(gelu_f(zz));
                 } else if (EPI == EPI_BIAS) {
-                    g.cf[(int64_t)m * g.ldcf + n] = v + g.bias[n];
+                    cf[(int64_t)m * g.ldcf + n] = v + g.bias[n];
                 } else if (EPI == EPI_F32) {
-                    g.cf[(int64_t)m * g.ldcf + n] = v;
+                    cf[(int64_t)m * g.ldcf + n] = v;
                 } else {
                     g.cb[(int64_t)m * g.ldcb + n] = f2bf(v * gelu_grad_f(g.z[(int64_t)m * g.ldz + n]));
                 }
             }
+}
+
+// out[m][n] = sum over the splits z = 0 .. S-1, in that order, of
+// part[z][m][n] (pitch N).
+__global__ __launch_bounds__(256) void reduce_splits_kernel(int M, int N, int S, const float *part, float *out,
+                                                            int64_t ldo)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    const int m = (int)(e / N), n = (int)(e - (int64_t)m * N);
+    float s = 0.0f;
+    for (int z = 0; z < S; ++z) s += part[(int64_t)z * M * N + e];
+    out[(int64_t)m * ldo + n] = s;
 }
 
 // ------------------------------------------------ loss, grads, AdamW ----
@@ -507,8 +596,49 @@ template <bool AT, bool BT, int EPI>
 int gemm(const GemmArgs &g, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0) return GM_OK;
-    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
+    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, 1);
     hipLaunchKernelGGL((gemm_kernel<AT, BT, EPI>), grid, dim3(256), 0, st, g);
+    return launch_gemm_rc();
+}
+
+// K splits of a weight-gradient product (C = A^T B over a long K, the
+// mini-batch): enough workgroups to fill the chip (the output has only
+// (M / 64) (N / 64) tiles: 136 for the first layer, 64 for the hidden ones)
+// while each split keeps at least 256 of K.
+int dw_splits(int M, int N, int K)
+{
+    const int tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    int s = 1;
+    while (s < 16 && tiles * s < 1024 && (K + 2 * s - 1) / (2 * s) >= 256) s *= 2;
+    return s;
+}
+
+size_t dw_part_floats(int M, int N, int K)
+{
+    const int s = dw_splits(M, N, K);
+    return s > 1 ? (size_t)s * M * N : 0;
+}
+
+// C (FP32, pitch ldcf) = A^T B with A(m, k) = a[k * lda + m] and B(k, n) =
+// b[bmap(k) * ldb + n]: the weight gradients.  With more than one split the
+// splits write partial sums to `part` (dw_part_floats(M, N, K) floats) and a
+// second kernel adds them in split order, so the result does not depend on
+// timing.
+int gemm_dw(GemmArgs g, float *part, hipStream_t st)
+{
+    if (g.M <= 0 || g.N <= 0) return GM_OK;
+    const int s = dw_splits(g.M, g.N, g.K);
+    if (s == 1) return gemm<true, false, EPI_F32>(g, st);
+    float *out = g.cf;
+    const int64_t ldo = g.ldcf;
+    g.cf = part;
+    g.ldcf = g.N;
+    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, s);
+    hipLaunchKernelGGL((gemm_kernel<true, false, EPI_F32>), grid, dim3(256), 0, st, g);
+    if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    const int64_t cnt = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, g.M, g.N, s,
+                       part, out, ldo);
     return launch_gemm_rc();
 }
 
@@ -562,6 +692,9 @@ size_t train_ws_bytes(const gm_mlp *m, int n)
     add((size_t)n * m->hidden * 2 * 2);     // dZ ping-pong
     add((size_t)kColSlices * NWAVE * std::max(m->hidden, m->out_dim) * 4);
     add((size_t)((n + 15) / 16) * 8);       // loss partials
+    size_t part = 0;                        // K-split partial sums of the weight gradients
+    for (int l = 0; l < L; ++l) part = std::max(part, dw_part_floats(layer_out(m, l), layer_in(m, l), n));
+    add(part * 4);
     return b + 256;
 }
 
@@ -585,6 +718,9 @@ int backward_pass(gm_ctx *c, const gm_mlp *m, int n, const uint16_t *x, int64_t 
     float *cpart = cv.take<float>((size_t)kColSlices * NWAVE * std::max(m->hidden, m->out_dim));
     const int nblk = (n + 15) / 16;
     double *lpart = cv.take<double>((size_t)nblk);
+    size_t npart = 0;
+    for (int l = 0; l < L; ++l) npart = std::max(npart, dw_part_floats(layer_out(m, l), layer_in(m, l), n));
+    float *dwpart = cv.take<float>(npart);
     rc = forward_pass(m, n, x, ldx, rows, Y, Z, out, st);
     if (rc) return rc;
     hipLaunchKernelGGL(mse_kernel, dim3(nblk), dim3(256), 0, st, n, m->out_dim, m->n_out, out, targets, rows, dout,
@@ -611,7 +747,7 @@ int backward_pass(gm_ctx *c, const gm_mlp *m, int n, const uint16_t *x, int64_t 
         g.bmap = l == 0 ? rows : nullptr;
         g.cf = m->grad + w_off(m, l);
         g.ldcf = nin;
-        rc = gemm<true, false, EPI_F32>(g, st);
+        rc = gemm_dw(g, dwpart, st);
         if (rc) return rc;
         hipLaunchKernelGGL(colsum_part_kernel, dim3((nout + 63) / 64, kColSlices), dim3(256), 0, st, n, nout, dcur,
                            ldd, cpart);
@@ -812,6 +948,44 @@ int gm_mlp_forward(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t *x,
     uint16_t *Y[17];
     for (int l = 0; l < mlp->n_hidden; ++l) Y[l] = buf[l & 1];
     return forward_pass(mlp, n, x, ldx, nullptr, Y, nullptr, out, (hipStream_t)stream);
+}
+
+int gm_mlp_gemm(gm_ctx *ctx, int32_t op, int32_t m, int32_t n, int32_t k, const uint16_t *a, int64_t lda,
+                const int32_t *a_rows, const uint16_t *b, int64_t ldb, const int32_t *b_rows, float *c,
+                int64_t ldc, void *stream)
+{
+    if (!ctx || m < 0 || n < 0 || k < 0 || op < GM_GEMM_NT || op > GM_GEMM_TN) return GM_EINVAL;
+    if (m == 0 || n == 0) return GM_OK;
+    if (!c || ldc < n || lda % 8 || ldb % 8) return GM_EINVAL;
+    if (k > 0 && (!a || !b || !aligned16(a) || !aligned16(b))) return GM_EINVAL;     // k = 0: C = 0, no reads
+    hipStream_t st = (hipStream_t)stream;
+    Scoped sd(ctx->device);
+    GemmArgs g{};
+    g.M = m;
+    g.N = n;
+    g.K = k;
+    g.a = a;
+    g.lda = lda;
+    g.b = b;
+    g.ldb = ldb;
+    g.cf = c;
+    g.ldcf = ldc;
+    if (op == GM_GEMM_NT) {
+        if (k % 8 || lda < k || ldb < k || b_rows) return GM_EINVAL;
+        g.amap = a_rows;
+        return gemm<false, true, EPI_F32>(g, st);
+    }
+    if (op == GM_GEMM_NN) {
+        if (k % 8 || n % 8 || lda < k || ldb < n || b_rows) return GM_EINVAL;
+        g.amap = a_rows;
+        return gemm<false, false, EPI_F32>(g, st);
+    }
+    if (m % 8 || n % 8 || lda < m || ldb < n || a_rows) return GM_EINVAL;
+    g.bmap = b_rows;
+    const size_t part = dw_part_floats(m, n, k);
+    int rc = ensure_ws(ctx, part * 4 + 256);
+    if (rc) return rc;
+    return gemm_dw(g, reinterpret_cast<float *>(ctx->mlp_ws), st);
 }
 
 int gm_mlp_backward(gm_ctx *ctx, const gm_mlp *mlp, int32_t n, const uint16_t *x, int64_t ldx, const int32_t *rows,

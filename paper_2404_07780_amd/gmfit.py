@@ -26,7 +26,7 @@ SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",
            "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_set_schedule",
            "gm_schedule_options", "gm_mlp_param_count", "gm_mlp_sync",
-           "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_features",
+           "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_mlp_gemm", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise",
            "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch", "gm_plan_elapsed", "gm_plan_destroy",
            "gm_bootstrap", "gm_fit_adam")
@@ -112,6 +112,7 @@ def lib() -> C.CDLL:
         L.gm_mlp_backward.argtypes = [v, p, i, v, i64, v, v, v, v]
         L.gm_mlp_adamw.argtypes = [v, p, i64, p, v]
         L.gm_mlp_train_step.argtypes = [v, p, i, v, i64, v, v, i64, p, v, v]
+        L.gm_mlp_gemm.argtypes = [v, i, i, i, i, v, i64, v, v, i64, v, v, i64, v]
         L.gm_features.argtypes = [v, p, p, v, i64, v, v]
         L.gm_proposal_targets.argtypes = [v, p, p, v, v, v, i, v]
         L.gm_proposal_decode.argtypes = [v, p, p, v, i, v, v, v, v]
@@ -127,7 +128,7 @@ def lib() -> C.CDLL:
         L.gm_plan_destroy.restype = None
         for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
-                     "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
+                     "gm_mlp_gemm", "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise", "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch",
                      "gm_plan_elapsed", "gm_bootstrap", "gm_fit_adam"):
             getattr(L, name).restype = i
@@ -506,6 +507,31 @@ def gm_mlp_backward(mlp: MLP, x: torch.Tensor, targets: torch.Tensor, rows: Opti
     _check("gm_mlp_backward", lib().gm_mlp_backward(ctx.handle, C.byref(m), n, _ptr(x), x.stride(0), _ptr(rows),
                                                     _ptr(targets), _ptr(loss), _stream()))
     return loss
+
+
+GEMM_NT, GEMM_NN, GEMM_TN = 0, 1, 2
+
+
+def gm_mlp_gemm(op: int, a: torch.Tensor, b: torch.Tensor, a_rows: Optional[torch.Tensor] = None,
+                b_rows: Optional[torch.Tensor] = None, ctx: Optional[Context] = None) -> torch.Tensor:
+    """FP32 product of two device BF16 matrices by the dense layers' kernels:
+    NT: a [m][k] (rows gathered by a_rows), b [n][k] -> a b^T; NN: a [m][k]
+    (a_rows), b [k][n] -> a b; TN: a [k][m], b [k][n] (rows gathered by b_rows)
+    -> a^T b."""
+    for t in (a, b):
+        if t.dtype != torch.bfloat16 or t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("operands must be 2-D BF16 tensors with unit column stride")
+    if op == GEMM_NT:
+        m, k, n = (a_rows.numel() if a_rows is not None else a.shape[0]), a.shape[1], b.shape[0]
+    elif op == GEMM_NN:
+        m, k, n = (a_rows.numel() if a_rows is not None else a.shape[0]), a.shape[1], b.shape[1]
+    else:
+        k, m, n = (b_rows.numel() if b_rows is not None else b.shape[0]), a.shape[1], b.shape[1]
+    ctx = _ctx_for(a.device, ctx)
+    c = torch.empty(m, n, dtype=torch.float32, device=a.device)
+    _check("gm_mlp_gemm", lib().gm_mlp_gemm(ctx.handle, op, m, n, k, _ptr(a), a.stride(0), _ptr(a_rows), _ptr(b),
+                                            b.stride(0), _ptr(b_rows), _ptr(c), c.stride(0), _stream()))
+    return c
 
 
 def gm_mlp_adamw(mlp: MLP, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,

@@ -23,7 +23,7 @@ from oracle import mlp as M
 from paper_2404_07780_amd import gmfit as G
 from paper_2404_07780_amd import learned as Lrn
 from paper_2404_07780_amd import synth as S
-from tests.gpu_helpers import oracle_batch, oracle_mixed, param_parity
+from tests.gpu_helpers import judge_batch, oracle_batch, oracle_mixed, param_parity
 from tests.oracle_models import from_spec
 from tests.philox_ref import galaxy_normals
 
@@ -93,6 +93,24 @@ def test_backward_matches_oracle():
             rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
             print(f"layer {l} {name}: rel err {rel:.2e}", flush=True)
             assert rel <= 2e-3, (l, name, rel)
+    # element by element: dW_l[o][i] = sum_m dZ_l[m][o] X_l[m][i] within 2^-7 of
+    # sum_m |dZ_l[m][o]| |X_l[m][i]| (a BF16 rounding of one dZ or X value landing on
+    # the other side of a tie moves the sum by 2^-8 of one term); an operand read
+    # from a wrong row, column or tile edge moves it by a large part of that sum
+    _, (acts, zs) = M.forward(flat.astype(np.float64), x, emulate_bf16=True)
+    layers = M.unpack(flat.astype(np.float64))
+    out, _ = M.forward(flat.astype(np.float64), x, emulate_bf16=True)
+    dz = np.zeros_like(out)
+    dz[:, :7] = 2.0 * (out[:, :7] - t[:, :7]) / (n * 7)
+    dz = M.bf16(dz)
+    for l in range(len(layers) - 1, -1, -1):
+        gW, gb = M.unpack(grad)[l]
+        bound = 2.0 ** -7 * (np.abs(dz).T @ np.abs(acts[l])) + 1e-30
+        ratio = np.abs(gW - M.unpack(rg)[l][0]) / bound
+        print(f"layer {l} W element-wise: worst {ratio.max():.3f} of the bar", flush=True)
+        assert np.all(ratio <= 1.0), (l, np.unravel_index(np.argmax(ratio), ratio.shape))
+        if l > 0:
+            dz = M.bf16(M.bf16(dz @ M.bf16(layers[l][0])) * M.gelu_grad(zs[l - 1]))
     gW, gb = M.unpack(grad)[-1]
     assert np.all(gW[7:] == 0) and np.all(gb[7:] == 0)
     # a row gather gives exactly the gradient of the gathered rows
@@ -205,16 +223,16 @@ def test_synth_noise_matches_philox_reference():
         assert mag[g, 0] == 0 and mag[g, 2] == 0
 
 
-def _judge(b, gp, gs):
-    """Parity of GPU fits with the oracle LM from the oracle's moment guess."""
+def _judge(b, gp, gc, gs):
+    """Parity of GPU fits with the oracle LM from the oracle's moment guess
+    (judge_fit on every galaxy both sides converge)."""
     om = from_spec(b.model)
     ostart, _ = O.default_guess_batch(om, b.h, b.w, b.img_off, b.data, b.sigma)
     rp, rc, rn, rs = O.fit_batch(om, b.h, b.w, b.img_off, b.data, b.sigma, b.psf_k, b.psf_off, b.psf, ostart)
     names = S.MODEL_SPECS[b.model]["names"]
-    both = (gs == 0) & (rs == 0)
-    npass = sum(int(param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))[0].all())
-                for g in np.where(both)[0])
-    return npass, int(both.sum()), rs, rn
+    npass, nboth, fails, counts = judge_batch(b, om, names, gp, gc, gs, rp, rc, rs)
+    print(f"  parity verdicts {counts}, fails {fails}", flush=True)
+    return npass, nboth, rs, rn
 
 
 def test_fit_learned_falls_back_on_invalid_proposals():
@@ -236,10 +254,10 @@ def test_fit_learned_from_untrained_network_matches_oracle():
     gm = G.Model.from_spec(S.MODEL_SPECS["sersic"])
     mlp = G.MLP(np.zeros(M.param_count(), np.float32), train=False)    # proposal = moments, n = e^0.6
     lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, _dev(b), mlp)]
-    npass, nboth, rs, _ = _judge(b, lp, ls)
+    npass, nboth, rs, _ = _judge(b, lp, lc, ls)
     print(f"untrained proposal: fallback {fb.sum()}/{b.n}, parity {npass}/{nboth}", flush=True)
     assert np.all(ls[fb == 0] == 0) and set(np.unique(fb)) <= {0, 1, 2}
-    assert nboth >= 0.8 * b.n and npass >= 0.9 * nboth
+    assert nboth >= 0.8 * b.n and npass == nboth
 
 
 def test_training_reduces_loss_and_iterations():
@@ -256,12 +274,12 @@ def test_training_reduces_loss_and_iterations():
     lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp)]
     start, _ = G.gm_default_guess(gm, db)
     dp, dc, dn, ds_ = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
-    npass, nboth, rs, rn = _judge(b, lp, ls)
+    npass, nboth, rs, rn = _judge(b, lp, lc, ls)
     print(f"held-out: iterations learned {ln.mean():.2f} (fallback {fb.sum()}) vs default {dn.mean():.2f} "
           f"(oracle {rn.mean():.2f}); converged learned {np.mean(ls == 0):.3f} default {np.mean(ds_ == 0):.3f}; "
           f"parity {npass}/{nboth}", flush=True)
     assert ln.mean() < dn.mean()
-    assert nboth >= 0.8 * b.n and npass >= 0.9 * nboth
+    assert nboth >= 0.8 * b.n and npass == nboth
 
 
 def test_proposal_trial_budget():

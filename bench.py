@@ -162,7 +162,7 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi:
     fits of the same data (plain, and learned when a network is given) are
     judged against it."""
     import oracle as O
-    from tests.gpu_helpers import oracle_batch, oracle_box_batch, oracle_shape_batch, param_parity
+    from tests.gpu_helpers import judge_batch, oracle_batch, oracle_box_batch, oracle_shape_batch
     from tests.oracle_models import from_spec
 
     ncores = len(os.sched_getaffinity(0))
@@ -181,26 +181,21 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi:
     dt = time.perf_counter() - t0
     names = S.MODEL_SPECS[b.model]["names"]
 
-    def judge(gp, gs):
-        both = (gs == 0) & (rs == 0)
-        npass, fails = 0, []
-        for g in np.where(both)[0]:
-            ok, worst = param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))
-            if ok.all():
-                npass += 1
-            else:
-                k = int(np.argmax(worst))
-                fails.append([int(g), names[k], round(float(worst[k]), 2), float(gp[g, k]), float(rp[g, k])])
-        return dict(both_converged=int(both.sum()), pass_1e4=int(npass), gpu_converged=int((gs == 0).sum()),
+    def judge(gp, gc, gs):
+        # every galaxy both sides converge, judged as in the parity tests: the 1e-4
+        # relative bar, or the stop test's sigma bar for undetermined parameters, or
+        # two minima on either side of a window step
+        npass, nboth, fails, counts = judge_batch(b, om, names, gp, gc, gs, rp, rc, rs)
+        return dict(both_converged=nboth, pass_1e4=npass, gpu_converged=int((gs == 0).sum()), verdicts=counts,
                     fails=fails[:8])
 
     start, _ = G.gm_default_guess(gm, db)
     gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
     parity = dict(sample=n_sample, oracle_converged=int((rs == 0).sum()), oracle_mean_iters=float(rn.mean()),
-                  plain=judge(gp, gs))
+                  plain=judge(gp, gc, gs))
     if mlp is not None:
         lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=pmi)]
-        parity["learned"] = judge(lp, ls)
+        parity["learned"] = judge(lp, lc, ls)
         parity["learned"]["fallback"] = int((fb != 0).sum())
     cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
                sample=f"galaxies 0..{n_sample - 1} of the workload (rendered and noised on the host), moment start "
@@ -583,12 +578,19 @@ def mixed_main(args, n: int, seed: int, chunks):
         del d["iters"]
     cpu = parity = None
     if args.cpu_sample != 0:
-        ns = 256 if args.cpu_sample is None else args.cpu_sample
+        ns = 1024 if args.cpu_sample is None else args.cpu_sample
         log(f"cpu baseline: oracle on mixed galaxies 0..{ns - 1}")
         cpu, parity = mixed_baseline(ns, seed, mlp, args.proposal_max_iter)
+    raw = n / (wall / args.steps)
+    gate = None
+    if parity is not None:
+        frac = sum(d["pass_1e4"] for d in parity["per_kind"].values()) / parity["sample"]
+        gate = dict(fraction=frac, rule="converged on both sides and within the parity bar of the oracle's fit, "
+                                        "over the oracle sample (all kinds)")
     outj = {
         "metric": "galaxies fitted/s (mixed profiles, learned-init LM for the Sersic parts, plain LM otherwise)",
-        "value": n / (wall / args.steps), "unit": "galaxies/s", "n_gpus": 1, "steps": args.steps,
+        "value": raw * (gate["fraction"] if gate else 1.0), "raw_value": raw, "gate": gate,
+        "unit": "galaxies/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"mixed: {WORKLOADS['mixed']['desc']}", "n_gal": n, "seed": seed,
@@ -612,7 +614,7 @@ def mixed_baseline(n_sample: int, seed: int, mlp, pmi: int):
     and is judged per kind: convergence of each side, parity of galaxies both
     converged."""
     import oracle as O
-    from tests.gpu_helpers import oracle_mixed, param_parity
+    from tests.gpu_helpers import judge_batch, oracle_mixed
     from tests.oracle_models import from_spec
 
     ncores = len(os.sched_getaffinity(0))
@@ -634,11 +636,9 @@ def mixed_baseline(n_sample: int, seed: int, mlp, pmi: int):
             start, _ = G.gm_default_guess(gm, db)
             gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
         names = S.MODEL_SPECS[b.model]["names"]
-        both = (gs == 0) & (rs == 0)
-        npass = sum(int(param_parity(names, gp[g], rp[g], sky_sigma=float(np.median(b.image(b.sigma, g))))[0].all())
-                    for g in np.where(both)[0])
+        npass, nboth, fails, counts = judge_batch(b, om, names, gp, gc, gs, rp, rc, rs)
         out[kind] = dict(n=int(b.n), gpu_converged=int((gs == 0).sum()), oracle_converged=int((rs == 0).sum()),
-                         both_converged=int(both.sum()), pass_1e4=int(npass))
+                         both_converged=nboth, pass_1e4=npass, verdicts=counts, fails=fails[:8])
     cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
                sample=f"mixed galaxies 0..{n_sample - 1} (rendered and noised on the host), moment start and LM, "
                       f"{dt:.1f} s")
@@ -873,9 +873,22 @@ def main():
                                    box=wl.get("box", False), shape=wl.get("shape"))
 
     key = f"{args.workload}:{n}:{seed}:{source_hash()}"
+    # The metric counts galaxies fitted to within the parity bar of the oracle: the raw
+    # rate times the fraction of the oracle sample that the GPU fitted (converged) and
+    # that passes against the oracle's fit (fits the oracle does not converge on count
+    # as failed).  Without an oracle sample the raw rate is reported as is.
+    gate = None
+    value = head["value"]
+    if parity is not None:
+        frac = parity["learned" if learned else "plain"]["pass_1e4"] / parity["sample"]
+        gate = dict(fraction=frac, rule="converged on both sides and within the parity bar of the oracle's fit, "
+                                        "over the oracle sample")
+        value = head["value"] * frac
     out = {
         "metric": METRIC,
-        "value": head["value"],
+        "value": value,
+        "raw_value": head["value"],
+        "gate": gate,
         "unit": "galaxies/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -909,10 +922,12 @@ def main():
                           "paper_galaxies_per_s": 8289 / 600.0, "paper_method": "gradient descent (torch)"}
     if learned:
         pl = results["plain"]
-        out["plain_lm"] = dict(value=pl["value"], ms_per_step=pl["ms_per_step"], lm_ms=pl["lm_ms"],
+        pfrac = parity["plain"]["pass_1e4"] / parity["sample"] if parity is not None else 1.0
+        out["plain_lm"] = dict(value=pl["value"] * pfrac, raw_value=pl["value"], ms_per_step=pl["ms_per_step"],
+                               lm_ms=pl["lm_ms"],
                                mean_iters=pl["mean_iters"], converged=pl["converged"],
                                roofline_frac=pl["achieved"] / PEAK_FP32_TFLOPS)
-        out["speedup_vs_plain"] = head["value"] / pl["value"]
+        out["speedup_vs_plain"] = value / out["plain_lm"]["value"]
         out["training"] = train_info
     print(json.dumps(out))
 

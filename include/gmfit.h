@@ -68,7 +68,7 @@ enum {
  *   GM_SKYPLANE sky kx ky                   Appendix D, eq. (new_sky_I): the tilted-plane
  *               sky + kx (x - W/2) + ky (y - H/2) about the cutout's centre, added after
  *               convolution (compiled with a single Sersic; other models GM_EUNSUPPORTED)
- * Boxiness is 0 (r_box = 1, eq. (rbox)). */
+ * Every profile other than the Sersic has boxiness 0 (r_box = 1, eq. (rbox)). */
 enum { GM_SERSIC = 1, GM_EXPDISK, GM_FERRER, GM_KING, GM_GAUSSIAN, GM_MOFFAT, GM_SKY, GM_SKYPLANE };
 
 typedef struct {
@@ -84,8 +84,8 @@ typedef struct {
     gm_component comp[4];
     int32_t p;                /* length of each galaxy's parameter vector, 1..16 */
     double m0;                /* magnitude zero point (22.5 in the paper's examples) */
-    int32_t oversample;       /* sub-samples per pixel side in the central window (10); 1 = off */
-    int32_t os_window;        /* side of the central window in pixels (5); odd, <= 7 */
+    int32_t oversample;       /* sub-samples per pixel side in the central window (10), 1..16; 1 = off */
+    int32_t os_window;        /* side of the central window in pixels (5); 0, or odd and <= 5 */
 } gm_model;
 
 typedef struct {

@@ -118,11 +118,18 @@ __host__ __device__ inline size_t planes_bytes(int K)
 }
 
 // ---------------------------------------------------------------- per-evaluation state in LDS
+// Tiles a thread sums its FP32 partial products of g and J^T W J over before
+// they are added, per wave, to FP64 running sums (EvalShared::nacc): a thread
+// then never sums more than 4 x 16 = 64 pixels in FP32, whatever the cutout's
+// size.  Cutouts of up to 16 tiles (128 x 128) never flush.
+constexpr int FLUSH_TILES = 16;
+
 template <class F>
 struct EvalShared {
     typename F::Prep prep;
     double win0[F::NCOMP][MAXWIN];
     float win[F::NCOMP][MAXWIN][F::ND];
+    double nacc[NWAVE][F::P + F::P * (F::P + 1) / 2];     // per-wave FP64 sums of the flushed partials
 };
 
 // scratch needed by the window tables (in the plane buffer)
@@ -502,7 +509,7 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     eval_prologue<F>(u, ma, H, W, sh, planes);
     const cfloat *psf = (const cfloat *)(ba.psf + uniform64(me.psf_off));
     // Per-thread partial sums: chi^2 in FP64 (it decides accept/reject), g and
-    // A in FP32 (a thread sums at most a few hundred pixels of them).
+    // A in FP32 over at most FLUSH_TILES tiles (64 pixels), then FP64.
     double c2 = 0.0;
     float red[NR - 1];
 #pragma unroll
@@ -510,8 +517,24 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     int r, cg;
     strip_of(tid, K, r, cg);
     const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
+    const int lane = tid & 63, wave = tid >> 6;
+    const bool flushes = nty * ntx > FLUSH_TILES;       // uniform over the workgroup
+    if (flushes && lane == 0)
+        for (int q = 0; q < NR - 1; ++q) sh.nacc[wave][q] = 0.0;
+    int since_flush = 0;
     for (int ty = 0; ty < nty; ++ty) {
         for (int tx = 0; tx < ntx; ++tx) {
+            if (since_flush == FLUSH_TILES) {
+                // the FP32 partials of the last FLUSH_TILES tiles into the wave's FP64 sums
+#pragma unroll
+                for (int q = 0; q < NR - 1; ++q) {
+                    const double v = wave_sum((double)red[q]);
+                    if (lane == 0) sh.nacc[wave][q] += v;
+                    red[q] = 0.0f;
+                }
+                since_flush = 0;
+            }
+            ++since_flush;
             const int ti0 = ty * TILE, tj0 = tx * TILE;
             double acc0[4];
             float acc[F::NPL][4];
@@ -551,7 +574,6 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     // fixed-order reduction in FP64: within each wave, then the waves in order
     // (the plane buffer is idle after the last tile's barrier: reuse it)
     double *sred = reinterpret_cast<double *>(planes);
-    const int lane = tid & 63, wave = tid >> 6;
     {
         double v = wave_sum(c2);
         if (lane == 0) sred[wave * NR] = v;
@@ -559,7 +581,7 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
 #pragma unroll
     for (int q = 1; q < NR; ++q) {
         double v = wave_sum((double)red[q - 1]);
-        if (lane == 0) sred[wave * NR + q] = v;
+        if (lane == 0) sred[wave * NR + q] = flushes ? sh.nacc[wave][q - 1] + v : v;
     }
     __syncthreads();
     for (int q = tid; q < NR; q += NT) {

@@ -126,7 +126,8 @@ def lib() -> C.CDLL:
         L.gm_fit_adam.argtypes = [v, p, p, p, v, v, v, v]
         L.gm_plan_destroy.argtypes = [v]
         L.gm_plan_destroy.restype = None
-        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_param_errors",
+        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch",
+                     "gm_param_errors",
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_mlp_gemm", "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
                      "gm_synth_noise", "gm_plan_fit", "gm_plan_fit_learned", "gm_plan_launch",

@@ -73,3 +73,37 @@ def test_max_size_fit_and_adam():
                                    start, steps=3)
     ok, worst = param_parity(NAMES, ap[0], op[0])
     assert ok.all(), worst
+
+
+def test_max_size_covariance_errors():
+    """Errors sqrt(diag (J^T W J)^-1) at 1024 x 1024 and 1024 x 333 (Sec. 5.2):
+    J^T W J sums a million pixels; each thread sums its FP32 partial products
+    over at most 16 tiles before they enter the FP64 sums, and the errors
+    (from gm_param_errors and from the fit kernel) hold the 1e-4 bar."""
+    print("max size: covariance errors 1024x1024, 1024x333", flush=True)
+    om = single(O.SERSIC, sky=True)
+    gm = to_gm(om)
+    shapes = [(1024, 1024), (1024, 333)]
+    # centres inside the cutouts (x0 runs over the 333 columns): the data then
+    # determine every parameter and J^T W J is well conditioned
+    params = np.array([[512.3, 511.6, 12.0, 40.0, 2.5, 0.6, 30.0, 100.0],
+                       [166.7, 511.2, 13.0, 25.0, 1.2, 0.4, 100.0, 50.0]])
+    rng = np.random.default_rng(93)
+    data = np.concatenate([(O.model_image(om, h, w, PSF, params[g]) + rng.normal(size=(h, w))).ravel()
+                           for g, (h, w) in enumerate(shapes)]).astype(np.float32)
+    b = _batch(shapes, data=data)
+    err, cov = G.gm_param_errors(gm, b, params, want_cov=True)
+    err, cov = err.cpu().numpy(), cov.cpu().numpy()
+    for g, (h, w) in enumerate(shapes):
+        o = int(b.img_off[g])
+        re, rcov = O.param_errors(om, data[o:o + h * w].reshape(h, w), np.ones((h, w), np.float32), PSF, params[g],
+                                  want_cov=True)
+        rel = np.abs(err[g] - re) / re
+        print(f"  {h}x{w}: worst relative error of the errors {rel.max():.2e}", flush=True)
+        assert np.all(rel <= 1e-4), (g, dict(zip(NAMES, rel)))
+        assert np.allclose(cov[g], rcov, rtol=1e-4, atol=1e-4 * np.sqrt(np.outer(re, re)).max())
+    # errors computed by the fit kernel at its end point: equal to gm_param_errors there
+    ef = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
+    p, c, it, st = G.gm_fit_batch(gm, b, params, err_out=ef)
+    ref = G.gm_param_errors(gm, b, p).cpu().numpy()
+    assert np.allclose(ef.cpu().numpy(), ref, rtol=1e-5, atol=0)

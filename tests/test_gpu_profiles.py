@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 import oracle as O
 from paper_2404_07780_amd import gmfit as G
 from paper_2404_07780_amd import synth as S
-from tests.gpu_helpers import image_parity, judge_fit, oracle_mixed, param_parity
+from tests.gpu_helpers import image_parity, judge_batch, oracle_mixed, param_parity
 from tests.oracle_models import from_spec, single, to_gm
 
 
@@ -111,15 +111,6 @@ def test_mixed_default_guess(mixed):
             assert np.allclose(mom[g], rm, rtol=1e-6, atol=1e-9), (kind, g)
 
 
-def _bar_vanished(names, p, sigma):
-    """The bar adds nothing to the model, so its flux and shape are not
-    identifiable: its r_out sits on the lower bound (0.1 px), where it covers
-    no sample point, or its total flux 10^(-0.4 (m - 22.5)) is below 1e-9 of
-    the pixel noise."""
-    flux = 10.0 ** (-0.4 * (p[names.index("mag_bar")] - 22.5))
-    return p[names.index("rout")] <= 0.1 + 1e-9 or flux <= 1e-9 * sigma
-
-
 @pytest.mark.parametrize("kind", ["sersic", "sersicbar", "king", "point"])
 def test_mixed_fit(mixed, kind):
     b = mixed[kind]
@@ -134,27 +125,10 @@ def test_mixed_fit(mixed, kind):
                                  omega=b.omega)
     names = S.MODEL_SPECS[b.model]["names"]
     both = (gs == 0) & (rs == 0)
-    npass, fails, counts = 0, [], {}
-    for g in np.where(both)[0]:
-        sigma = b.image(b.sigma, g)
-        sig = float(np.median(sigma))
-        if kind == "sersicbar" and _bar_vanished(names, rp[g], sig):
-            # compare the identifiable part (Sersic + sky); the GPU's bar must have vanished too
-            unique = [k for k, nm in enumerate(names) if nm not in ("mag_bar", "rout", "q_bar", "pa_bar")]
-            ok, worst = param_parity([names[k] for k in unique], gp[g, unique], rp[g, unique], sky_sigma=sig)
-            ok, how = bool(ok.all()) and _bar_vanished(names, gp[g], sig), "vanished bar"
-            ok = ok and abs(gc[g] - rc[g]) <= 1e-6 * rc[g]
-            worst = float(worst.max())
-        else:
-            ok, how, worst = judge_fit(om, names, b.image(b.data, g), sigma, b.psf_of(g), gp[g], rp[g], gc[g], rc[g],
-                                       omega=b.image(b.omega, g))
-        counts[how] = counts.get(how, 0) + 1
-        if ok:
-            npass += 1
-        else:
-            fails.append((int(g), round(worst, 2)))
-            print(f"  fail g={g}: gpu {np.round(gp[g], 5).tolist()} chi2 {gc[g]:.9g} iters {gn[g]}\n"
-                  f"            orc {np.round(rp[g], 5).tolist()} chi2 {rc[g]:.9g} iters {rn[g]}", flush=True)
+    npass, nboth, fails, counts = judge_batch(b, om, names, gp, gc, gs, rp, rc, rs)
+    for g, _ in fails:
+        print(f"  fail g={g}: gpu {np.round(gp[g], 5).tolist()} chi2 {gc[g]:.9g} iters {gn[g]}\n"
+              f"            orc {np.round(rp[g], 5).tolist()} chi2 {rc[g]:.9g} iters {rn[g]}", flush=True)
     print(f"mixed fit parity [{kind}]: {npass}/{int(both.sum())} pass {counts} of {b.n}; gpu converged "
           f"{np.mean(gs == 0):.3f} oracle {np.mean(rs == 0):.3f}; iters gpu {gn.mean():.1f} oracle {rn.mean():.1f}; "
           f"fails {fails[:4]}", flush=True)

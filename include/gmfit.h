@@ -188,6 +188,26 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                  const gm_fit_opts *opts, double *params_inout, double *chi2_out,
                  int32_t *niter_out, int32_t *status_out, void *stream);
 
+/* gm_fit_batch for callers that cannot allocate (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, bit for bit, with the per-call device metadata (sizes, fit order,
+ * work-queue counter) in a fixed device array of the library (about 4 MB per
+ * GPU, held until the process ends) instead of the context's grow-only
+ * workspace.  No hipMalloc, hipFree or host pinned allocation is made; the
+ * host size arrays of the batch are copied to the device with
+ * hipMemcpyAsync on `stream` (pageable source: the runtime has copied it
+ * when the call returns).  The context must exist (gm_create, which resolves
+ * the array on its device).  Galaxies are fitted in index order rather than
+ * largest first (same per-galaxy results, other load balance).  At most
+ * GM_NOALLOC_MAX_GAL galaxies (GM_EINVAL beyond).  Every call on one GPU uses
+ * that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other contexts, other host threads) race and must be serialised by the
+ * caller; stream-ordered calls on one stream are safe. */
+#define GM_NOALLOC_MAX_GAL 65536
+int gm_fit_batch_noalloc(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
+                         const gm_fit_opts *opts, double *params_inout, double *chi2_out,
+                         int32_t *niter_out, int32_t *status_out, void *stream);
+
 /* Covariance errors sigma_p = sqrt(diag (J^T W J)^-1), W = Omega / sigma^2
  * (Sec. 5.2), unscaled, in natural units at params (device [n_gal][p]).
  * err_out: device [n_gal][p]; cov_out (nullable): device [n_gal][p][p].

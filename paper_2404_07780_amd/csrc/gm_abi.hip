@@ -11,12 +11,75 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "gm_launch.h"
 
 using namespace gm;
+
+// Device scratch of gm_fit_batch_noalloc, for callers that cannot allocate:
+// per galaxy its Meta record (32 B), its fit order (4 B) and the raw size
+// metadata copied from the caller's host arrays (h, w, PSF side: 4 B each;
+// image and PSF offsets: 8 B each), plus the work-queue counter.  Every GPU
+// holds its own copy until the process ends; host code reaches it only
+// through the address resolved per device at context set-up.
+constexpr int kNoAllocMaxGal = GM_NOALLOC_MAX_GAL;
+constexpr size_t kNaMeta = (size_t)kNoAllocMaxGal * sizeof(Meta);
+constexpr size_t kNaOrder = (size_t)kNoAllocMaxGal * sizeof(int32_t);
+constexpr size_t kNaQueue = 256;
+constexpr size_t kNaRaw32 = (size_t)kNoAllocMaxGal * sizeof(int32_t);
+constexpr size_t kNaRaw64 = (size_t)kNoAllocMaxGal * sizeof(int64_t);
+constexpr size_t kNoAllocBytes = kNaMeta + kNaOrder + kNaQueue + 3 * kNaRaw32 + 2 * kNaRaw64;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices];        // device address of `scratch` on each GPU
+std::mutex g_scratch_mu;
+
+// With `device` current: resolve the device address of `scratch` once.
+int resolve_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return GM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return GM_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GM_EHIP;
+    g_scratch[device] = ptr;
+    return GM_OK;
+}
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
+
+// Meta records of the raw host-copied sizes, the identity fit order and a
+// zero work-queue counter (a kernel, not a memset: callers may capture it).
+__global__ void noalloc_pack_kernel(int n, int convolved, const int32_t *h, const int32_t *w, const int32_t *k,
+                                    const int64_t *img_off, const int64_t *psf_off, Meta *meta, int *order,
+                                    int *queue)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0;
+    if (i >= n) return;
+    Meta m;
+    m.h = h[i];
+    m.w = w[i];
+    m.k = convolved ? k[i] : 1;
+    m.pad = 0;
+    m.img_off = img_off[i];
+    m.psf_off = convolved ? psf_off[i] : 0;
+    meta[i] = m;
+    order[i] = i;
+}
+
+}  // namespace
 
 namespace gm {
 
@@ -150,6 +213,10 @@ int ctx_init(gm_ctx *c, int device)
         return GM_EHIP;
     }
     c->num_cu = prop.multiProcessorCount;
+    if (resolve_scratch(device) != GM_OK) {
+        ctx_release(c);
+        return GM_EHIP;
+    }
     return GM_OK;
 }
 
@@ -406,7 +473,7 @@ int match_model(const gm_model *m, Match &out)
         }
     }
     // every column must be referenced by some slot
-    std::vector<int> seen(m->p, 0);
+    int seen[MAXP] = {};
     for (int i = 0; i < m->n_comp; ++i)
         for (int s = 0; s < kSlots[m->comp[i].type]; ++s)
             if (m->comp[i].param_index[s] >= 0) seen[m->comp[i].param_index[s]] = 1;
@@ -478,7 +545,7 @@ int match_model(const gm_model *m, Match &out)
         ops = family_table(b->type == GM_EXPDISK ? FAM_BULGEDISK : FAM_SERSICBAR);
     }
     // a column used by two internal variables would be an unsupported tie
-    std::vector<int> used(m->p, 0);
+    int used[MAXP] = {};
     for (int k = 0; k < nint; ++k)
         if (ma.col[k] >= 0 && used[ma.col[k]]++) return GM_EUNSUPPORTED;
     out.ops = ops;
@@ -759,6 +826,53 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, cons
     const Variant *v;
     if ((rc = pick_variant(ctx, mt, &v))) return rc;
     return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, nullptr, (hipStream_t)stream);
+}
+
+int gm_fit_batch_noalloc(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_fit_opts *opts,
+                         double *params_inout, double *chi2_out, int32_t *niter_out, int32_t *status_out,
+                         void *stream)
+{
+    Match mt;
+    int rc = prologue(ctx, model, batch, mt);
+    if (rc) return rc;
+    if (opts && (opts->max_iter < 0 || !(opts->lambda0 > 0.0) || !(opts->step_tol > 0.0))) return GM_EINVAL;
+    if (batch->n_gal > kNoAllocMaxGal) return GM_EINVAL;
+    if (batch->n_gal == 0) return GM_OK;
+    if (!params_inout || !chi2_out || !niter_out || !status_out) return GM_EINVAL;
+    Scoped sd(ctx->device);
+    char *base = reinterpret_cast<char *>(scratch_of(ctx->device));
+    if (!base) return GM_EHIP;
+    const Variant *v;
+    if ((rc = pick_variant(ctx, mt, &v))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const int n = batch->n_gal;
+    Meta *meta = reinterpret_cast<Meta *>(base);
+    int *order = reinterpret_cast<int *>(base + kNaMeta);
+    int *queue = reinterpret_cast<int *>(base + kNaMeta + kNaOrder);
+    char *raw = base + kNaMeta + kNaOrder + kNaQueue;
+    int32_t *rh = reinterpret_cast<int32_t *>(raw);
+    int32_t *rw = reinterpret_cast<int32_t *>(raw + kNaRaw32);
+    int32_t *rk = reinterpret_cast<int32_t *>(raw + 2 * kNaRaw32);
+    int64_t *rio = reinterpret_cast<int64_t *>(raw + 3 * kNaRaw32);
+    int64_t *rpo = reinterpret_cast<int64_t *>(raw + 3 * kNaRaw32 + kNaRaw64);
+    const size_t n4 = sizeof(int32_t) * (size_t)n, n8 = sizeof(int64_t) * (size_t)n;
+    if (hipMemcpyAsync(rh, batch->h, n4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(rw, batch->w, n4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(rio, batch->img_off, n8, hipMemcpyHostToDevice, st) != hipSuccess)
+        return GM_EHIP;
+    if (mt.ci.convolved && (hipMemcpyAsync(rk, batch->psf_k, n4, hipMemcpyHostToDevice, st) != hipSuccess ||
+                            hipMemcpyAsync(rpo, batch->psf_off, n8, hipMemcpyHostToDevice, st) != hipSuccess))
+        return GM_EHIP;
+    hipLaunchKernelGGL(noalloc_pack_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, mt.ci.convolved ? 1 : 0,
+                       rh, rw, rk, rio, rpo, meta, order, queue);
+    if ((rc = hip_rc(hipGetLastError()))) return rc;
+    Staged sg;
+    sg.meta = meta;
+    sg.extra = order;
+    sg.queue = queue;
+    FitExtra ex;
+    ex.pre = &sg;
+    return v->fit(ctx, mt.ci, opts, params_inout, chi2_out, niter_out, status_out, &ex, st);
 }
 
 int gm_fit_adam(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const gm_adam_opts *opts,

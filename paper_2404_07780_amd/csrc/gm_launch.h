@@ -69,22 +69,26 @@ struct CallInfo {
     int wpc = 0;          // persistent workgroups per CU (0: as many as are resident)
 };
 
+// Device workspace of one call: [meta | extra | queue counter].
+struct Staged {
+    Meta *meta;
+    void *extra;
+    int *queue;
+};
+
 // Optional parts of a fit launch (FitArgs): the refit of galaxies whose first
-// fit does not converge, and bootstrap replicas.
+// fit does not converge, bootstrap replicas, and metadata already on the
+// device.
 struct FitExtra {
+    // non-null: meta, fit order (extra) and a zeroed queue counter already on
+    // the device (gm_fit_batch_noalloc); no host ordering and no staging
+    const Staged *pre = nullptr;
     const double *refit_start = nullptr;   // [n_gal][p] start of the refit
     const int *valid = nullptr;            // nullable: 0 = the first start is unusable
     int *refit_code = nullptr;             // nullable: 0 / 1 / 2 per galaxy
     int first_max_iter = 0;                // trials of the first fit
     int n_boot = 0;                        // > 0: n_boot replicas of each galaxy
     uint64_t boot_seed = 0;
-};
-
-// Device workspace of one call: [meta | extra | queue counter].
-struct Staged {
-    Meta *meta;
-    void *extra;
-    int *queue;
 };
 
 // defined in gm_abi.hip
@@ -239,20 +243,25 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     // fit indices: the galaxies, or n_boot replicas of each (i -> galaxy i / n_boot)
     const int nb = (ex && ex->n_boot > 0) ? ex->n_boot : 1;
     const int nfit = b->n_gal * nb;
-    // longest-processing-time order: biggest cutouts (times PSF area) first
-    std::vector<int> order(nfit);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(b->n_gal);
-    for (int g = 0; g < b->n_gal; ++g) {
-        double k = ci.convolved ? b->psf_k[g] : 1.0;
-        cost[g] = (double)b->h[g] * b->w[g] * k * k;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x / nb] > cost[y / nb]; });
     Staged sg;
-    rc = stage(c, ci, order.data(), sizeof(int) * (size_t)nfit, st, &sg);
-    if (rc) return rc;
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
-    if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    if (ex && ex->pre) {
+        if (nb != 1) return GM_EINVAL;
+        sg = *ex->pre;
+    } else {
+        // longest-processing-time order: biggest cutouts (times PSF area) first
+        std::vector<int> order(nfit);
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<double> cost(b->n_gal);
+        for (int g = 0; g < b->n_gal; ++g) {
+            double k = ci.convolved ? b->psf_k[g] : 1.0;
+            cost[g] = (double)b->h[g] * b->w[g] * k * k;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x / nb] > cost[y / nb]; });
+        rc = stage(c, ci, order.data(), sizeof(int) * (size_t)nfit, st, &sg);
+        if (rc) return rc;
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
+        if (hipGetLastError() != hipSuccess) return GM_EHIP;
+    }
     FitArgs fa{};
     fa.order = reinterpret_cast<const int *>(sg.extra);
     fa.active = o ? o->active : nullptr;

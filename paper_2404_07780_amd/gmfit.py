@@ -24,7 +24,7 @@ SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 
 # exported symbols (one per declaration of include/gmfit.h)
 SYMBOLS = ("gm_create", "gm_destroy", "gm_error_string", "gm_model_image", "gm_jacobian",
-           "gm_default_guess", "gm_fit_batch", "gm_param_errors", "gm_model_vjp", "gm_set_schedule",
+           "gm_default_guess", "gm_fit_batch", "gm_fit_batch_noalloc", "gm_param_errors", "gm_model_vjp", "gm_set_schedule",
            "gm_schedule_options", "gm_mlp_param_count", "gm_mlp_sync",
            "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step", "gm_mlp_gemm", "gm_features",
            "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned", "gm_synth_noise",
@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
         L.gm_jacobian.argtypes = [v, p, p, v, v, v]
         L.gm_default_guess.argtypes = [v, p, p, v, v, v]
         L.gm_fit_batch.argtypes = [v, p, p, p, v, v, v, v, v]
+        L.gm_fit_batch_noalloc.argtypes = [v, p, p, p, v, v, v, v, v]
         L.gm_param_errors.argtypes = [v, p, p, v, v, v, v]
         L.gm_model_vjp.argtypes = [v, p, p, v, v, v, v]
         L.gm_set_schedule.argtypes = [v, p, i, p]
@@ -126,7 +127,7 @@ def lib() -> C.CDLL:
         L.gm_fit_adam.argtypes = [v, p, p, p, v, v, v, v]
         L.gm_plan_destroy.argtypes = [v]
         L.gm_plan_destroy.restype = None
-        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch",
+        for name in ("gm_model_image", "gm_jacobian", "gm_default_guess", "gm_fit_batch", "gm_fit_batch_noalloc",
                      "gm_param_errors",
                      "gm_model_vjp", "gm_set_schedule", "gm_schedule_options", "gm_mlp_sync", "gm_mlp_forward", "gm_mlp_backward", "gm_mlp_adamw", "gm_mlp_train_step",
                      "gm_mlp_gemm", "gm_features", "gm_proposal_targets", "gm_proposal_decode", "gm_fit_learned",
@@ -376,6 +377,29 @@ def gm_fit_batch(model: Model, batch: Batch, params0, max_iter: int = 100, lambd
     _check("gm_fit_batch", lib().gm_fit_batch(ctx.handle, C.byref(m), C.byref(b), C.byref(o), _ptr(params),
                                               _ptr(chi2), _ptr(niter), _ptr(status), _stream()))
     return params, chi2, niter, status
+
+
+NOALLOC_MAX_GAL = 65536
+
+
+def gm_fit_batch_noalloc(model: Model, batch: Batch, params: torch.Tensor, chi2: torch.Tensor,
+                         niter: torch.Tensor, status: torch.Tensor, max_iter: int = 100, lambda0: float = 1e-3,
+                         step_tol: float = 1e-4, ctx: Optional[Context] = None, active=None,
+                         err_out: Optional[torch.Tensor] = None) -> None:
+    """gm_fit_batch without any allocation, into the caller's device tensors:
+    params (float64 [n, p], the start on entry, the fit on return), chi2
+    (float64 [n]), niter and status (int32 [n])."""
+    ctx = ctx or context(batch.device.index)
+    for t, dt, shape in ((params, torch.float64, (batch.n, model.p)), (chi2, torch.float64, (batch.n,)),
+                         (niter, torch.int32, (batch.n,)), (status, torch.int32, (batch.n,))):
+        if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous() or t.device != batch.device:
+            raise ValueError("outputs must be contiguous device tensors of the batch's sizes")
+    o = gm_fit_opts(int(max_iter), float(lambda0), float(step_tol), None if active is None else active.data_ptr(), 0,
+                    _err_ptr(err_out, batch, model))
+    m, b = model.c(), batch.c()
+    _check("gm_fit_batch_noalloc", lib().gm_fit_batch_noalloc(ctx.handle, C.byref(m), C.byref(b), C.byref(o),
+                                                              _ptr(params), _ptr(chi2), _ptr(niter), _ptr(status),
+                                                              _stream()))
 
 
 def gm_fit_adam(model: Model, batch: Batch, params0, steps: int = 1000, lr: float = 0.01, beta1: float = 0.9,

@@ -49,7 +49,9 @@ enum {
     GM_ST_CONVERGED = 0,  /* Gauss-Newton step below step_tol in units of the covariance errors */
     GM_ST_MAXITER = 1,    /* max_iter trials used */
     GM_ST_STALLED = 2,    /* damping exceeded 1e9 */
-    GM_ST_NONFINITE = 3   /* chi^2 at the start vector is not finite */
+    GM_ST_NONFINITE = 3,  /* chi^2 at the start vector is not finite */
+    GM_ST_TEAM_TIMEOUT = 4 /* a fit shared by several workgroups lost a member (gm_schedule.team):
+                              a wait passed its limit; the parameters are the last accepted point */
 };
 
 /* Profile types (Sec. 4): natural parameter slots of each, in order
@@ -145,10 +147,27 @@ int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
  *     one pass through LDS (fewer groups: less re-evaluation of the profile,
  *     more LDS per workgroup); 0 = the library's default;
  *   wg_per_cu -- persistent workgroups per compute unit, at most as many as
- *     are resident; 0 = as many as are resident. */
+ *     are resident; 0 = as many as are resident;
+ *   team -- workgroups per fit (the paper's Sec. 7 notes that small batches
+ *     leave the GPU idle): the G workgroups of a fit share each model
+ *     evaluation, tile by tile, and the leader adds their FP64 partial sums
+ *     in a fixed order before the LM step (results then differ from one
+ *     workgroup's in the last bits of the sums, the fit itself is the same
+ *     method).  0 = automatic: when a launch has fewer fits than resident
+ *     workgroups, each fit gets min(32, resident / fits, its tiles); 1 = one
+ *     workgroup per fit; k > 1 = min(k, tiles) workgroups for every fit of at
+ *     least team_min_tiles 32 x 32 tiles, one for the others;
+ *   team_min_tiles -- see team (0 = 1);
+ *   team_wait_us -- bound of every wait between the workgroups of a team, in
+ *     microseconds (0 = 20 s); a fit whose team passes it ends with
+ *     GM_ST_TEAM_TIMEOUT (the waits always end: a team's workgroups are
+ *     resident together). */
 typedef struct {
     int32_t plane_groups;
     int32_t wg_per_cu;
+    int32_t team;
+    int32_t team_min_tiles;
+    int32_t team_wait_us;
 } gm_schedule;
 
 /* Use `sched` for models of the same family as `model` whose batches have
@@ -189,11 +208,12 @@ int gm_fit_batch(gm_ctx *ctx, const gm_model *model, const gm_batch *batch,
                  int32_t *niter_out, int32_t *status_out, void *stream);
 
 /* gm_fit_batch for callers that cannot allocate (code under stream capture,
- * tight serving loops, harnesses that forbid hipMalloc): the same kernels and
- * results, bit for bit, with the per-call device metadata (sizes, fit order,
- * work-queue counter) in a fixed device array of the library (about 4 MB per
- * GPU, held until the process ends) instead of the context's grow-only
- * workspace.  No hipMalloc, hipFree or host pinned allocation is made; the
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels,
+ * one workgroup per fit (gm_schedule.team does not apply), with results bit
+ * for bit those of gm_fit_batch under team = 1, and the per-call device
+ * metadata (sizes, fit order, work-queue counter) in a fixed device array of
+ * the library (about 4 MB per GPU, held until the process ends) instead of
+ * the context's grow-only workspace.  No hipMalloc, hipFree or host pinned allocation is made; the
  * host size arrays of the batch are copied to the device with
  * hipMemcpyAsync on `stream` (pageable source: the runtime has copied it
  * when the call returns).  The context must exist (gm_create, which resolves

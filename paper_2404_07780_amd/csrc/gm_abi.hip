@@ -137,6 +137,23 @@ int ensure_aux(gm_ctx *c, size_t bytes, void **out)
     return GM_OK;
 }
 
+int ensure_team(gm_ctx *c, size_t bytes, void **out)
+{
+    if (c->team_bytes < bytes) {
+        if (c->team) {
+            if (hipDeviceSynchronize() != hipSuccess) return GM_EHIP;
+            (void)hipFree(c->team);
+            c->team = nullptr;
+            c->team_bytes = 0;
+        }
+        size_t nb = std::max(bytes, (size_t)1 << 20);
+        if (hipMalloc(&c->team, nb) != hipSuccess) return GM_ENOMEM;
+        c->team_bytes = nb;
+    }
+    *out = c->team;
+    return GM_OK;
+}
+
 int stage(gm_ctx *c, const CallInfo &ci, const void *extra, size_t extra_bytes, hipStream_t st, Staged *out)
 {
     const gm_batch *b = ci.b;
@@ -213,6 +230,9 @@ int ctx_init(gm_ctx *c, int device)
         return GM_EHIP;
     }
     c->num_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+    c->wall_hz = (int64_t)khz * 1000;
     if (resolve_scratch(device) != GM_OK) {
         ctx_release(c);
         return GM_EHIP;
@@ -227,11 +247,12 @@ void ctx_release(gm_ctx *c)
     if (c->unit_psf) (void)hipFree(c->unit_psf);
     if (c->mlp_ws) (void)hipFree(c->mlp_ws);
     if (c->aux) (void)hipFree(c->aux);
+    if (c->team) (void)hipFree(c->team);
     if (c->staged) (void)hipEventDestroy(c->staged);
-    c->dev = c->host = c->mlp_ws = c->aux = nullptr;
+    c->dev = c->host = c->mlp_ws = c->aux = c->team = nullptr;
     c->unit_psf = nullptr;
     c->staged = nullptr;
-    c->dev_bytes = c->host_bytes = c->mlp_ws_bytes = c->aux_bytes = 0;
+    c->dev_bytes = c->host_bytes = c->mlp_ws_bytes = c->aux_bytes = c->team_bytes = 0;
 }
 
 namespace {
@@ -262,9 +283,17 @@ int plan_open(gm_ctx *parent, int n_gal, int stages, bool timing, gm_plan **out)
         return rc;
     }
     p->ctx.sched = parent->sched;
-    // per staging: metadata, the largest extra a plan stages (the LPT order)
+    // per staging: metadata, the largest extra a plan stages (the LPT order, or
+    // the queue entries of fits shared by teams of workgroups: at most the
+    // largest team size of the schedules per fit, or fits + 4096 in the
+    // automatic mode, which forms teams only below the resident workgroups)
     // and the queue counter
-    const size_t per = align256(sizeof(Meta) * (size_t)n_gal) + align256(sizeof(int) * (size_t)n_gal) + 256;
+    size_t team_cap = 1;
+    for (const auto &e : parent->sched)
+        if (e.team > 1) team_cap = std::max(team_cap, (size_t)std::min(e.team, 32));
+    const size_t items = std::max((size_t)n_gal * team_cap, (size_t)n_gal + 4096);
+    const size_t extra = std::max(sizeof(int) * (size_t)n_gal, sizeof(TeamItem) * items);
+    const size_t per = align256(sizeof(Meta) * (size_t)n_gal) + align256(extra) + 256;
     p->cap.bytes = per * (size_t)stages;
     try {
         p->cap.image.assign(p->cap.bytes, 0);
@@ -591,7 +620,13 @@ int pick_variant(gm_ctx *c, Match &mt, const Variant **out)
     for (const auto &e : c->sched)
         if (e.family == f->id && (e.k == K || (e.k == 0 && !hit))) hit = &e;
     mt.ci.wpc = 0;
+    mt.ci.team = 0;
+    mt.ci.team_min = 1;
+    mt.ci.team_wait_us = 0;
     if (hit) {
+        mt.ci.team = hit->team;
+        mt.ci.team_min = std::max(hit->team_min, 1);
+        mt.ci.team_wait_us = hit->team_wait_us;
         for (int i = 0; i < f->n; ++i)
             if (f->v[i].ng == hit->ng || hit->ng == 0) {
                 if (f->v[i].lds(K) > kMaxLds) break;
@@ -746,7 +781,7 @@ int gm_jacobian(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const
 int gm_set_schedule(gm_ctx *ctx, const gm_model *model, int32_t psf_k, const gm_schedule *sched)
 {
     if (!ctx || !sched || psf_k < 0 || (psf_k > 0 && (psf_k & 1) == 0) || sched->plane_groups < 0 ||
-        sched->wg_per_cu < 0)
+        sched->wg_per_cu < 0 || sched->team < 0 || sched->team_min_tiles < 0 || sched->team_wait_us < 0)
         return GM_EINVAL;
     Match mt;
     int rc = match_model(model, mt);
@@ -761,9 +796,13 @@ int gm_set_schedule(gm_ctx *ctx, const gm_model *model, int32_t psf_k, const gm_
         if (e.family == mt.ops->id && e.k == k) {
             e.ng = sched->plane_groups;
             e.wpc = sched->wg_per_cu;
+            e.team = sched->team;
+            e.team_min = sched->team_min_tiles;
+            e.team_wait_us = sched->team_wait_us;
             return GM_OK;
         }
-    ctx->sched.push_back({mt.ops->id, k, sched->plane_groups, sched->wg_per_cu});
+    ctx->sched.push_back({mt.ops->id, k, sched->plane_groups, sched->wg_per_cu, sched->team, sched->team_min_tiles,
+                          sched->team_wait_us});
     return GM_OK;
 }
 

@@ -497,10 +497,14 @@ __device__ inline void boot_weights(const BootArgs &bt, int64_t pix0, float (&m)
 // One model evaluation at u (LDS): chi^2, g = J^T W r and A = J^T W J
 // (internal LM variables), written to out_chi2/out_g/out_A (LDS, A full
 // P x P).  All threads of the workgroup call it.
+//
+// A team of tsize workgroups shares one evaluation: the workgroup of rank
+// trank takes the tiles whose row-major index is trank modulo tsize, and its
+// outputs are the partial sums over those tiles (tsize = 1: the whole image).
 template <class F, int KT, int NG>
 __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &ba, const Meta &me, EvalShared<F> &sh,
                          float *planes, double *out_chi2, double *out_g, double *out_A,
-                         const BootArgs &bt = BootArgs{0u, 0u, 0, -1})
+                         const BootArgs &bt = BootArgs{0u, 0u, 0, -1}, int trank = 0, int tsize = 1)
 {
     constexpr int P = F::P;
     constexpr int NR = 1 + P + P * (P + 1) / 2;
@@ -518,12 +522,15 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     strip_of(tid, K, r, cg);
     const int nty = (H + TILE - 1) / TILE, ntx = (W + TILE - 1) / TILE;
     const int lane = tid & 63, wave = tid >> 6;
-    const bool flushes = nty * ntx > FLUSH_TILES;       // uniform over the workgroup
+    const int ntiles = nty * ntx;
+    const int mine = (ntiles - trank + tsize - 1) / tsize;        // tiles of this workgroup
+    const bool flushes = mine > FLUSH_TILES;                      // uniform over the workgroup
     if (flushes && lane == 0)
         for (int q = 0; q < NR - 1; ++q) sh.nacc[wave][q] = 0.0;
     int since_flush = 0;
-    for (int ty = 0; ty < nty; ++ty) {
-        for (int tx = 0; tx < ntx; ++tx) {
+    for (int ti = trank; ti < ntiles; ti += tsize) {
+        {
+            const int ty = ti / ntx, tx = ti - ty * ntx;
             if (since_flush == FLUSH_TILES) {
                 // the FP32 partials of the last FLUSH_TILES tiles into the wave's FP64 sums
 #pragma unroll
@@ -799,6 +806,7 @@ struct LMShared {
     int freev[F::P];
     int t, status, fresh, apd, action, max_iter;
     int gal;
+    int tok;                  // team: the last wait ended in time
 };
 
 struct FitArgs {
@@ -825,9 +833,98 @@ struct FitArgs {
     // i / n_boot (BootArgs, key (boot_k0, boot_k1)); n_gal counts fit indices.
     int n_boot;
     uint32_t boot_k0, boot_k1;
+    // Teams (nullable items): queue entry i is items[i] instead of order[i];
+    // n_gal then counts the entries.  A fit with team size G > 1 is served by
+    // G workgroups through its TeamCtl (ctl[team]) and its G partial-sum
+    // slots (part + team * part_stride + rank * NR); spin_limit bounds every
+    // wait of a team member, in wall-clock ticks.
+    const struct TeamItem *items;
+    struct TeamCtl *ctl;
+    double *part;
+    int64_t part_stride;
+    int64_t spin_limit;
 };
 
 enum { ACT_EVAL = 0, ACT_RETRY = 1, ACT_DONE = 2 };
+
+// ---------------------------------------------------------------- teams of workgroups
+// A fit served by G workgroups: the leader (rank 0) runs the LM, and each
+// evaluation is shared by the team -- the leader publishes the point (its
+// LM variables and the command ACT_EVAL, epoch by epoch), every member
+// evaluates its tiles and delivers its partial sums (chi^2, g, the lower
+// triangle of A in FP64), the leader adds the G partials in rank order (a
+// fixed order: results do not depend on timing) and takes the LM step.  The
+// leader ends the team with ACT_DONE.  All G workgroups hold their queue
+// entries at once (consecutive entries of the persistent grid, which is never
+// smaller than a team), so every wait ends; each wait is nonetheless bounded
+// by spin_limit, after which the fit ends with GM_ST_TEAM_TIMEOUT.
+struct TeamItem {
+    int32_t fit, rank, size, team;
+};
+
+struct TeamCtl {
+    int cmd;                  // commands published so far (the epoch of the last one + 1)
+    int action;               // the last command: ACT_EVAL or ACT_DONE
+    int arrive;               // partial sums delivered so far, over all epochs
+    int pad;
+    double u[MAXP];           // the point of the last ACT_EVAL
+};
+
+__device__ inline int team_load(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until *p >= target (acquire) or the limit passes; true if reached.
+__device__ inline bool team_wait(const int *p, int target, int64_t limit)
+{
+    const int64_t t0 = wall_clock64();
+    while (team_load(p) < target) {
+        if (wall_clock64() - t0 > limit) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Entry q of the NR = 1 + P + P (P + 1) / 2 sums of an evaluation: chi^2, g,
+// then A's lower triangle row by row.
+template <int P>
+__device__ inline double sum_entry(int q, double chi2, const double *g, const double *A)
+{
+    if (q == 0) return chi2;
+    if (q <= P) return g[q - 1];
+    int e = q - 1 - P, k = 0;
+    while ((k + 1) * (k + 2) / 2 <= e) ++k;
+    return A[k * P + (e - k * (k + 1) / 2)];
+}
+
+template <int P>
+__device__ inline void set_entry(int q, double v, double *chi2, double *g, double *A)
+{
+    if (q == 0) {
+        *chi2 = v;
+    } else if (q <= P) {
+        g[q - 1] = v;
+    } else {
+        int e = q - 1 - P, k = 0;
+        while ((k + 1) * (k + 2) / 2 <= e) ++k;
+        const int l = e - k * (k + 1) / 2;
+        A[k * P + l] = v;
+        A[l * P + k] = v;
+    }
+}
+
+// All threads: this workgroup's partial sums (LDS) into its slot, made visible
+// at device scope before thread 0 counts the delivery.
+template <int P>
+__device__ inline void team_deliver(TeamCtl *ctl, double *slot, double chi2, const double *g, const double *A)
+{
+    constexpr int NR = 1 + P + P * (P + 1) / 2;
+    for (int q = threadIdx.x; q < NR; q += NT) slot[q] = sum_entry<P>(q, chi2, g, A);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctl->arrive, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------- wave-parallel LM step
 // One wave runs the LM bookkeeping between evaluations.  Lane r < P holds row
@@ -1139,6 +1236,68 @@ __host__ __device__ constexpr int min_wg()
     return F::NCOMP == 1 ? 2 : 1;
 }
 
+// Team steps around the one evaluation site of lm_fit_kernel.
+// Leader: publish the point s.ut of the epoch-th shared evaluation.
+template <class F>
+__device__ inline void team_publish(const LMShared<F> &s, TeamCtl *ctl, int epoch)
+{
+    const int tid = threadIdx.x;
+    if (tid < F::P) ctl->u[tid] = s.ut[tid];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        ctl->action = ACT_EVAL;
+        __hip_atomic_store(&ctl->cmd, epoch + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Member: wait for the leader's command of the epoch-th evaluation; s.action
+// and (for ACT_EVAL) s.ut take it.  A wait past the spin limit reads as ACT_DONE.
+template <class F>
+__device__ inline void team_command(LMShared<F> &s, const TeamCtl *ctl, int epoch, int64_t limit)
+{
+    if (threadIdx.x == 0) {
+        // the command's fields are read atomically (never through a cache of
+        // uniform loads), after the acquire of cmd
+        const bool got = team_wait(&ctl->cmd, epoch + 1, limit);
+        const int act = got ? __hip_atomic_load(&ctl->action, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ACT_DONE;
+        s.action = act;
+        if (act == ACT_EVAL)
+            for (int k = 0; k < F::P; ++k)
+                s.ut[k] = __hip_atomic_load(&ctl->u[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+// Leader, after its own delivery: wait for the team's tsize deliveries of the
+// epoch-th evaluation and add the partial sums in rank order into s.chi2t,
+// s.gt, s.At.  False if they did not arrive within the limit.
+template <class F>
+__device__ inline bool team_collect(LMShared<F> &s, TeamCtl *ctl, const double *slots, int tsize, int epoch,
+                                    int64_t limit)
+{
+    constexpr int P = F::P, NR = 1 + P + P * (P + 1) / 2;
+    const int tid = threadIdx.x;
+    if (tid == 0) s.tok = team_wait(&ctl->arrive, tsize * (epoch + 1), limit) ? 1 : 0;
+    __syncthreads();
+    const bool ok = uniform(s.tok) != 0;
+    if (ok) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (int q = tid; q < NR; q += NT) {
+            double v = slots[q];
+            for (int r = 1; r < tsize; ++r) v += slots[(int64_t)r * NR + q];
+            set_entry<P>(q, v, &s.chi2t, s.gt, s.At);
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+// Persistent LM fits: each workgroup takes queue entries (a fit, or one rank
+// of a team sharing a fit) until the queue is empty.  One workgroup, or the
+// leader of a team, runs the LM of its fit (a fit from params, then possibly
+// the refit from refit_start); members follow the leader's commands.  The
+// model is evaluated at a single site for all three roles.
 template <class F, int KT, int NG>
 __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, FitArgs fa)
 {
@@ -1146,13 +1305,23 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
     float *planes = reinterpret_cast<float *>(dyn_lds);
     __shared__ EvalShared<F> esh;
     __shared__ LMShared<F> s;
+    constexpr int NR = 1 + F::P + F::P * (F::P + 1) / 2;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) s.gal = atomicAdd(fa.queue, 1);
         __syncthreads();
         const int qi = uniform(s.gal);
         if (qi >= fa.n_gal) break;
-        const int g = uniform(fa.order[qi]);
+        int g, trank = 0, tsize = 1, team = 0;
+        if (fa.items) {
+            const TeamItem it = fa.items[qi];
+            g = uniform(it.fit);
+            trank = uniform(it.rank);
+            tsize = uniform(it.size);
+            team = uniform(it.team);
+        } else {
+            g = uniform(fa.order[qi]);
+        }
         if (fa.active && uniform(fa.active[g]) == 0) {
             __syncthreads();      // s.gal is rewritten by thread 0 next
             continue;
@@ -1160,45 +1329,81 @@ __global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs
         const int src = fa.n_boot > 0 ? g / fa.n_boot : g;
         const BootArgs bt{fa.boot_k0, fa.boot_k1, src, fa.n_boot > 0 ? g - src * fa.n_boot : -1};
         const Meta me = ba.meta[src];
+        const bool member = trank > 0;
+        TeamCtl *ctl = tsize > 1 ? fa.ctl + team : nullptr;
+        double *slots = tsize > 1 ? fa.part + (int64_t)team * fa.part_stride : nullptr;
         // phase 0: the fit from params; phase 1: the refit from refit_start
         const bool refit = fa.refit_start != nullptr;
-        const int first = (refit && fa.valid && uniform(fa.valid[g]) == 0) ? 1 : 0;
-        int t0 = 0;
-        for (int phase = first; phase < 2; ++phase) {
-            if (tid == 0) {
-                load_u<F>(s, ma, (phase ? fa.refit_start : fa.params) + (int64_t)g * ma.p);
-                clamp_u<F>(s.u, me.h, me.w);
-                for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
-                s.t = -1;             // -1: the next evaluation is the start point
-                s.status = GM_ST_MAXITER;
-                s.max_iter = (refit && phase == 0) ? fa.first_max_iter : fa.max_iter;
-                s.lambda = fa.lambda0;
-                s.fresh = 1;
-                s.apd = 0;
-                s.chi2 = 0.0;
-                s.action = ACT_EVAL;
-                for (int k = 0; k < F::P; ++k) {
-                    s.Dg[k] = 1.0;
-                    s.sig[k] = 1.0;
+        const int first = (!member && refit && fa.valid && uniform(fa.valid[g]) == 0) ? 1 : 0;
+        int t0 = 0, phase = first, epoch = 0;
+        bool phase_start = !member;
+        for (;;) {
+            if (phase_start) {
+                if (tid == 0) {
+                    load_u<F>(s, ma, (phase ? fa.refit_start : fa.params) + (int64_t)g * ma.p);
+                    clamp_u<F>(s.u, me.h, me.w);
+                    for (int k = 0; k < F::P; ++k) s.ut[k] = s.u[k];
+                    s.t = -1;             // -1: the next evaluation is the start point
+                    s.status = GM_ST_MAXITER;
+                    s.max_iter = (refit && phase == 0) ? fa.first_max_iter : fa.max_iter;
+                    s.lambda = fa.lambda0;
+                    s.fresh = 1;
+                    s.apd = 0;
+                    s.chi2 = 0.0;
+                    s.action = ACT_EVAL;
+                    for (int k = 0; k < F::P; ++k) {
+                        s.Dg[k] = 1.0;
+                        s.sig[k] = 1.0;
+                    }
                 }
-            }
-            __syncthreads();
-            // one evaluation site: the start point first, then one trial per pass
-            while (s.action != ACT_DONE) {
-                if (s.action == ACT_EVAL)
-                    evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At, bt);
-                if (tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
                 __syncthreads();
+                phase_start = false;
             }
-            if (phase == 0) {
+            if (member) team_command<F>(s, ctl, epoch, fa.spin_limit);
+            const int act = uniform(s.action);
+            if (act == ACT_DONE) {
+                if (member) break;
+                if (uniform(s.status) == GM_ST_TEAM_TIMEOUT || phase == 1) break;
                 if (!refit || uniform(s.status) == GM_ST_CONVERGED) {
                     t0 = -1;          // no refit
                     break;
                 }
                 t0 = uniform(s.t);
                 __syncthreads();      // every thread has read s before thread 0 reloads it
+                phase = 1;
+                phase_start = true;
+                continue;
             }
+            if (act == ACT_EVAL) {
+                if (tsize > 1 && !member) team_publish<F>(s, ctl, epoch);
+                // the evaluation site: the whole image, or this rank's tiles of it
+                evaluate<F, KT, NG>(s.ut, ma, ba, me, esh, planes, &s.chi2t, s.gt, s.At, bt, trank, tsize);
+                if (tsize > 1) {
+                    team_deliver<F::P>(ctl, slots + (int64_t)trank * NR, s.chi2t, s.gt, s.At);
+                    if (!member && !team_collect<F>(s, ctl, slots, tsize, epoch, fa.spin_limit)) {
+                        if (tid == 0) {
+                            s.status = GM_ST_TEAM_TIMEOUT;
+                            s.action = ACT_DONE;
+                        }
+                        __syncthreads();
+                        continue;
+                    }
+                    ++epoch;
+                }
+            }
+            if (!member && tid < 64) lm_step_wave<F>(s, fa, me.h, me.w);
+            __syncthreads();
         }
+        if (member) {
+            __syncthreads();          // s.gal is rewritten by thread 0 next
+            continue;
+        }
+        if (tsize > 1 && tid == 0) {
+            // end the team (epoch + 2 exceeds every epoch a member can be waiting for)
+            ctl->action = ACT_DONE;
+            __hip_atomic_store(&ctl->cmd, epoch + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (uniform(s.status) == GM_ST_TEAM_TIMEOUT) t0 = -1;
         if (tid == 0) {
             double nat[F::P];
             canonical_nat<F>(s.u, s.freev, nat);
@@ -1520,5 +1725,11 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
 }
 
 static __global__ void fill_int_kernel(int *p, int v) { *p = v; }
+
+static __global__ void fill_ints_kernel(int *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 }  // namespace gm

@@ -26,8 +26,11 @@ struct gm_ctx {
     size_t mlp_ws_bytes = 0;
     void *aux = nullptr;          // grow-only device scratch (adjoint partial sums)
     size_t aux_bytes = 0;
+    void *team = nullptr;         // grow-only device scratch of fits shared by teams of workgroups
+    size_t team_bytes = 0;
+    int64_t wall_hz = 0;          // rate of the device's wall clock (team waits)
     struct Sched {
-        int family, k, ng, wpc;
+        int family, k, ng, wpc, team, team_min, team_wait_us;
     };
     std::vector<Sched> sched;     // gm_set_schedule entries
     // Set while a plan is being captured into a graph: staging then carves the
@@ -67,6 +70,9 @@ struct CallInfo {
     ModelArgs ma;
     bool convolved;
     int wpc = 0;          // persistent workgroups per CU (0: as many as are resident)
+    int team = 0;         // workgroups per fit: 0 automatic, 1 one, k > 1 up to k (gm_schedule)
+    int team_min = 1;     // fits with fewer tiles keep one workgroup when team > 1
+    int team_wait_us = 0; // bound of a team's waits (0: 20 s)
 };
 
 // Device workspace of one call: [meta | extra | queue counter].
@@ -97,6 +103,7 @@ int batch_kt(const CallInfo &ci);
 int max_k(const CallInfo &ci);
 // grow-only device scratch of the context (stream-ordered reuse)
 int ensure_aux(gm_ctx *c, size_t bytes, void **out);
+int ensure_team(gm_ctx *c, size_t bytes, void **out);
 // context set-up and release (gm_create, gm_destroy and plans)
 int ctx_init(gm_ctx *c, int device);
 void ctx_release(gm_ctx *c);
@@ -144,6 +151,14 @@ int prepare(Kern kern, size_t lds, int *blocks_per_cu)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds) != hipSuccess) return GM_EHIP;
     *blocks_per_cu = std::max(nb, 1);
     return GM_OK;
+}
+
+// Workgroups of lm_fit_kernel<F, KT, NG> resident per CU at `lds` bytes of
+// dynamic LDS.
+template <class F, int NG, int KT>
+int resident_fit(size_t lds, int *per_cu)
+{
+    return prepare(lm_fit_kernel<F, KT, NG>, lds, per_cu);
 }
 
 template <class F, int NG, int KT>
@@ -200,6 +215,7 @@ template <class F, int NG, int... KTS>
 struct Dispatch;
 template <class F, int NG>
 struct Dispatch<F, NG> {
+    static int resident(int, size_t lds, int *per_cu) { return resident_fit<F, NG, 0>(lds, per_cu); }
     template <class... A> static int fit(int, A &&...a) { return launch_fit<F, NG, 0>(a...); }
     template <class... A> static int adam(int, A &&...a) { return launch_adam<F, NG, 0>(a...); }
     template <class... A> static int err(int, A &&...a) { return launch_err<F, NG, 0>(a...); }
@@ -207,6 +223,10 @@ struct Dispatch<F, NG> {
 };
 template <class F, int NG, int K0, int... KR>
 struct Dispatch<F, NG, K0, KR...> {
+    static int resident(int kt, size_t lds, int *per_cu)
+    {
+        return kt == K0 ? resident_fit<F, NG, K0>(lds, per_cu) : Dispatch<F, NG, KR...>::resident(kt, lds, per_cu);
+    }
     template <class... A> static int fit(int kt, A &&...a)
     {
         return kt == K0 ? launch_fit<F, NG, K0>(a...) : Dispatch<F, NG, KR...>::fit(kt, a...);
@@ -244,6 +264,12 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
     const int nb = (ex && ex->n_boot > 0) ? ex->n_boot : 1;
     const int nfit = b->n_gal * nb;
     Staged sg;
+    const int kt = batch_kt(ci);
+    int n_items = nfit;
+    TeamItem *teams_items = nullptr;
+    TeamCtl *team_ctl = nullptr;
+    double *team_part = nullptr;
+    int64_t part_stride = 0;
     if (ex && ex->pre) {
         if (nb != 1) return GM_EINVAL;
         sg = *ex->pre;
@@ -257,15 +283,67 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
             cost[g] = (double)b->h[g] * b->w[g] * k * k;
         }
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x / nb] > cost[y / nb]; });
-        rc = stage(c, ci, order.data(), sizeof(int) * (size_t)nfit, st, &sg);
-        if (rc) return rc;
+        // workgroups per fit (gm_schedule.team); a team is never larger than 32, so
+        // that its workgroups are resident together whatever else runs on the GPU
+        std::vector<int> tsz(nfit, 1);
+        int gmax = 1, n_teams = 0;
+        if (ci.team != 1) {
+            int per_cu = 1;
+            if ((rc = Dispatch<F, NG, KTS...>::resident(kt, lds, &per_cu))) return rc;
+            if (ci.wpc > 0) per_cu = std::min(per_cu, ci.wpc);
+            const int R = per_cu * std::max(c->num_cu, 1);
+            for (int i = 0; i < nfit; ++i) {
+                const int g = i / nb;
+                const int tiles = ((b->h[g] + TILE - 1) / TILE) * ((b->w[g] + TILE - 1) / TILE);
+                int G = 1;
+                if (ci.team == 0)
+                    G = nfit < R ? std::min({32, R / nfit, tiles}) : 1;
+                else if (tiles >= ci.team_min)
+                    G = std::min({ci.team, 32, tiles});
+                tsz[i] = std::max(1, std::min(G, R));
+                gmax = std::max(gmax, tsz[i]);
+            }
+        }
+        if (gmax > 1) {
+            std::vector<TeamItem> items;
+            items.reserve(nfit);
+            for (int i : order) {
+                const int G = tsz[i];
+                const int team = G > 1 ? n_teams++ : 0;
+                for (int r = 0; r < G; ++r) items.push_back(TeamItem{i, r, G, team});
+            }
+            n_items = (int)items.size();
+            constexpr int NR = 1 + F::P + F::P * (F::P + 1) / 2;
+            part_stride = (int64_t)gmax * NR;
+            const size_t ctl_bytes = (sizeof(TeamCtl) * (size_t)n_teams + 255) & ~(size_t)255;
+            void *tw = nullptr;
+            if ((rc = ensure_team(c, ctl_bytes + sizeof(double) * (size_t)part_stride * n_teams, &tw))) return rc;
+            team_ctl = reinterpret_cast<TeamCtl *>(tw);
+            team_part = reinterpret_cast<double *>(reinterpret_cast<char *>(tw) + ctl_bytes);
+            rc = stage(c, ci, items.data(), sizeof(TeamItem) * items.size(), st, &sg);
+            if (rc) return rc;
+            teams_items = reinterpret_cast<TeamItem *>(sg.extra);
+            const int nwords = (int)(sizeof(TeamCtl) / sizeof(int)) * n_teams;
+            hipLaunchKernelGGL(fill_ints_kernel, dim3((nwords + 255) / 256), dim3(256), 0, st,
+                               reinterpret_cast<int *>(team_ctl), nwords, 0);
+            if (hipGetLastError() != hipSuccess) return GM_EHIP;
+        } else {
+            rc = stage(c, ci, order.data(), sizeof(int) * (size_t)nfit, st, &sg);
+            if (rc) return rc;
+        }
         hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, sg.queue, 0);
         if (hipGetLastError() != hipSuccess) return GM_EHIP;
     }
     FitArgs fa{};
-    fa.order = reinterpret_cast<const int *>(sg.extra);
+    fa.order = teams_items ? nullptr : reinterpret_cast<const int *>(sg.extra);
+    fa.items = teams_items;
+    fa.ctl = team_ctl;
+    fa.part = team_part;
+    fa.part_stride = part_stride;
+    const int64_t hz = std::max<int64_t>(c->wall_hz, 1000000);
+    fa.spin_limit = ci.team_wait_us > 0 ? std::max<int64_t>(1, hz * ci.team_wait_us / 1000000) : 20 * hz;
     fa.active = o ? o->active : nullptr;
-    fa.n_gal = nfit;
+    fa.n_gal = n_items;
     fa.queue = sg.queue;
     fa.params = params;
     fa.chi2 = chi2;
@@ -284,7 +362,7 @@ int run_fit(gm_ctx *c, const CallInfo &ci, const gm_fit_opts *o, double *params,
         fa.boot_k0 = (uint32_t)ex->boot_seed;
         fa.boot_k1 = (uint32_t)(ex->boot_seed >> 32);
     }
-    return Dispatch<F, NG, KTS...>::fit(batch_kt(ci), c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
+    return Dispatch<F, NG, KTS...>::fit(kt, c, ci.ma, batch_args(c, ci, sg), fa, lds, ci.wpc, st);
 }
 
 template <class F, int NG, int... KTS>

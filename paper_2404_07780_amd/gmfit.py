@@ -19,7 +19,7 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libgmfit.so")
 
 GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_EUNSUPPORTED = 0, -1, -2, -3, -4
-ST_CONVERGED, ST_MAXITER, ST_STALLED, ST_NONFINITE = 0, 1, 2, 3
+ST_CONVERGED, ST_MAXITER, ST_STALLED, ST_NONFINITE, ST_TEAM_TIMEOUT = 0, 1, 2, 3, 4
 SERSIC, EXPDISK, FERRER, KING, GAUSSIAN, MOFFAT, SKY, SKYPLANE = range(1, 9)
 
 # exported symbols (one per declaration of include/gmfit.h)
@@ -65,7 +65,8 @@ class gm_fit_opts(C.Structure):
 
 
 class gm_schedule(C.Structure):
-    _fields_ = [("plane_groups", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("plane_groups", C.c_int32), ("wg_per_cu", C.c_int32), ("team", C.c_int32),
+                ("team_min_tiles", C.c_int32), ("team_wait_us", C.c_int32)]
 
 
 class gm_mlp(C.Structure):
@@ -310,11 +311,15 @@ def gm_jacobian(model: Model, batch: Batch, params, ctx: Optional[Context] = Non
     return out
 
 
-def gm_set_schedule(model: Model, psf_k: int, plane_groups: int = 0, wg_per_cu: int = 0,
-                    ctx: Optional[Context] = None) -> None:
+def gm_set_schedule(model: Model, psf_k: int, plane_groups: int = 0, wg_per_cu: int = 0, team: int = 0,
+                    team_min_tiles: int = 0, team_wait_us: int = 0, ctx: Optional[Context] = None) -> None:
+    """Schedule of the model's family at PSF side psf_k (0: every side without
+    one): plane groups, persistent workgroups per CU, workgroups per fit
+    (team: 0 automatic, 1 one, k > 1 up to k for fits of at least
+    team_min_tiles tiles) and the bound of a team's waits (0: 20 s)."""
     ctx = ctx or context()
     m = model.c()
-    sc = gm_schedule(int(plane_groups), int(wg_per_cu))
+    sc = gm_schedule(int(plane_groups), int(wg_per_cu), int(team), int(team_min_tiles), int(team_wait_us))
     _check("gm_set_schedule", lib().gm_set_schedule(ctx.handle, C.byref(m), int(psf_k), C.byref(sc)))
 
 

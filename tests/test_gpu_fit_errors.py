@@ -2,10 +2,13 @@
 normal matrix of its last accepted evaluation: equal to gm_param_errors at the
 fitted canonical parameters (which the parity tests hold to the oracle) within
 1e-5 relative, also for fits that end with q > 1 and are put in canonical form
-and for fixed slots -- the two sum FP32 products of derivative images at
-points one rounding apart (the natural parameters round-trip through the LM
-variables), which the inverse amplifies to ~1e-6; and, end to end, within
-1e-3 of the oracle's errors at the oracle's own fit."""
+and for fixed slots -- with one workgroup per fit the two sum the same FP32
+products of derivative images at points one rounding apart (the natural
+parameters round-trip through the LM variables), which the inverse amplifies
+to ~1e-6 (a fit shared by a team groups its FP32 partial sums by rank, a
+difference the inverse amplifies by the conditioning of J^T W J, measured up
+to 8e-5); and, end to end with the default schedule, within 1e-3 of the
+oracle's errors at the oracle's own fit."""
 RTOL = 1e-5
 import numpy as np
 import pytest
@@ -23,6 +26,18 @@ from tests.oracle_models import from_spec
 
 def _dev(b):
     return G.Batch(b.h, b.w, b.img_off, b.psf_k, b.psf_off, b.data, b.sigma, b.psf, omega=b.omega)
+
+
+@pytest.fixture()
+def one_wg():
+    """A context that runs one workgroup per fit (gm_schedule.team = 1) for
+    every model these tests use."""
+    ctx = G.Context()
+    for name in ("sersic", "bulgedisk", "sersicbar"):
+        for k in (0, 15, 25):
+            G.gm_set_schedule(G.Model.from_spec(S.MODEL_SPECS[name]), k, team=1, ctx=ctx)
+    yield ctx
+    ctx.close()
 
 
 def _close(a, b, rtol):
@@ -43,16 +58,16 @@ def _flipped(start, names):
 
 
 @pytest.mark.parametrize("cfg,n", [("sersic64", 40), ("uneven", 8)])
-def test_fit_errors_equal_param_errors(cfg, n):
+def test_fit_errors_equal_param_errors(cfg, n, one_wg):
     b = oracle_batch(cfg, n, seed=41)
     gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
     names = S.MODEL_SPECS[b.model]["names"]
     db = _dev(b)
-    start = G.gm_default_guess(gm, db)[0].cpu().numpy()
+    start = G.gm_default_guess(gm, db, ctx=one_wg)[0].cpu().numpy()
     start[1::2] = _flipped(start[1::2], names)          # odd galaxies start with q > 1
     err = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
-    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err)
-    ref = G.gm_param_errors(gm, db, p).cpu().numpy()
+    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err, ctx=one_wg)
+    ref = G.gm_param_errors(gm, db, p, ctx=one_wg).cpu().numpy()
     got, pn = err.cpu().numpy(), p.cpu().numpy()
     ok, worst = _close(got, ref, RTOL)
     ipa = names.index("pa")
@@ -65,7 +80,7 @@ def test_fit_errors_equal_param_errors(cfg, n):
     assert nflip >= 1
 
 
-def test_fit_errors_fixed_slots():
+def test_fit_errors_fixed_slots(one_wg):
     # n fixed at 4 and sky fixed: a 6-column parameter vector
     b = oracle_batch("sersic64", 8, seed=42)
     gm = G.Model([G.Component(S.SERSIC, True, [0, 1, 2, 3, -1, 4, 5], [0, 0, 0, 0, 4.0, 0, 0]),
@@ -73,22 +88,22 @@ def test_fit_errors_fixed_slots():
     start = b.truth[:, [0, 1, 2, 3, 5, 6]].copy()
     db = _dev(b)
     err = torch.empty(b.n, 6, dtype=torch.float64, device="cuda")
-    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err)
-    ref = G.gm_param_errors(gm, db, p).cpu().numpy()
+    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err, ctx=one_wg)
+    ref = G.gm_param_errors(gm, db, p, ctx=one_wg).cpu().numpy()
     ok, worst = _close(err.cpu().numpy(), ref, RTOL)
     assert ok, worst
 
 
-def test_fit_errors_learned_path():
+def test_fit_errors_learned_path(one_wg):
     b = oracle_batch("sersic64", 32, seed=43)
     gm = G.Model.from_spec(S.MODEL_SPECS["sersic"])
     db = _dev(b)
     mlp = G.MLP(np.zeros(M.param_count(), np.float32), train=False)
     err = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
-    p, c, it, st, fb = G.gm_fit_learned(gm, db, mlp, proposal_max_iter=10, err_out=err)
+    p, c, it, st, fb = G.gm_fit_learned(gm, db, mlp, proposal_max_iter=10, err_out=err, ctx=one_wg)
     fbn = fb.cpu().numpy()
     assert (fbn == 0).any() and (fbn == 2).any()
-    ref = G.gm_param_errors(gm, db, p).cpu().numpy()
+    ref = G.gm_param_errors(gm, db, p, ctx=one_wg).cpu().numpy()
     ok, worst = _close(err.cpu().numpy(), ref, RTOL)
     assert ok, worst
 
@@ -173,7 +188,7 @@ def test_param_errors_two_components(model):
 
 
 @pytest.mark.parametrize("model", ["bulgedisk", "sersicbar"])
-def test_fit_errors_two_components(model):
+def test_fit_errors_two_components(model, one_wg):
     """Errors computed by the fit kernel at p = 12, with the canonical-form
     flip of each component carried through the covariance: equal to
     gm_param_errors at the fitted canonical parameters (1e-5), and
@@ -193,9 +208,9 @@ def test_fit_errors_two_components(model):
     start = ostart.copy()
     start[1::2] = _flip_all(start[1::2], names, model)      # odd galaxies start with q > 1
     err = torch.empty(b.n, gm.p, dtype=torch.float64, device="cuda")
-    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err)
+    p, c, it, st = G.gm_fit_batch(gm, db, start, err_out=err, ctx=one_wg)
     pn = p.cpu().numpy()
-    ref = G.gm_param_errors(gm, db, p).cpu().numpy()
+    ref = G.gm_param_errors(gm, db, p, ctx=one_wg).cpu().numpy()
     # the bar's normal matrix is ill-conditioned (two flat directions between the
     # Sersic and the bar): the parameters' round trip through the LM variables
     # moves it by ~1e-7 and its inverse by the condition number times that

@@ -1,7 +1,7 @@
 """Launch schedules: every compiled plane-group variant and workgroups-per-CU
 setting gives fits within the parity bar of the oracle (both from the
-oracle's moment start); the grid size does not change a galaxy's result; the
-tuner picks, applies and caches a schedule."""
+oracle's moment start); with one workgroup per fit the grid size does not
+change a galaxy's result; the tuner picks, applies and caches a schedule."""
 import json
 
 import numpy as np
@@ -38,7 +38,7 @@ def test_every_schedule_matches_oracle(cfg, n):
     for ng in opts:
         res = {}
         for wpc in (0, 1):
-            G.gm_set_schedule(gm, k, ng, wpc, ctx=ctx)
+            G.gm_set_schedule(gm, k, ng, wpc, team=1, ctx=ctx)     # one workgroup per fit
             res[wpc] = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, ostart, ctx=ctx)]
         for a, c in zip(res[0], res[1]):
             assert np.array_equal(a, c), (cfg, ng)

@@ -46,6 +46,62 @@ __host__ __device__ inline double dnat_du(int kind, double p)
     return 1.0;
 }
 
+// ---------------------------------------------------------------- FP64 point functions
+// Base-2 exponential and logarithm of the FP64 light at every region and
+// window point (the library's exp and log are general-purpose and several
+// times longer).  Both are within about 2 ulp of the exact values.
+//
+// 2^x: x = k + f with k = rint(x), |f| <= 1/2, 2^f = e^y with y = f ln 2,
+// |y| <= 0.347, by its Taylor series to y^12 (remainder below 1e-17), scaled
+// by 2^k (k clamped: 2^x is 0 or infinite there; a NaN x gives NaN).
+__host__ __device__ inline double exp2_pt(double x)
+{
+    const double k = rint(x);
+    const double y = (x - k) * kLn2;
+    double p = 1.0 / 479001600.0;
+    p = fma(p, y, 1.0 / 39916800.0);
+    p = fma(p, y, 1.0 / 3628800.0);
+    p = fma(p, y, 1.0 / 362880.0);
+    p = fma(p, y, 1.0 / 40320.0);
+    p = fma(p, y, 1.0 / 5040.0);
+    p = fma(p, y, 1.0 / 720.0);
+    p = fma(p, y, 1.0 / 120.0);
+    p = fma(p, y, 1.0 / 24.0);
+    p = fma(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    p = fma(p, y, 1.0);
+    return ldexp(p, (int)fmin(fmax(k, -2200.0), 2200.0));
+}
+
+// log2 x for finite x > 0: x = m 2^e with m in [1/sqrt 2, sqrt 2), and
+// ln m = 2 atanh s = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
+// |s| <= 3 - 2 sqrt 2, summed to s^23 (remainder below 1e-18).
+__host__ __device__ inline double log2_pt(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    return (double)e + s * (p * (2.0 * kLog2e));
+}
+
 // ---------------------------------------------------------------- FP64 scalars
 // digamma for x > 0: upward recurrence to x >= 10, then the Stirling series.
 __device__ inline double digamma(double x)
@@ -322,7 +378,7 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 struct Sersic {
     struct K {
         Geo g;
-        double lnIe, b, inv2n, lnre2;
+        double lnIe, b, inv2n, lnre2, lnIe2, b2, l2re2;
         float bf, inv2nf, l2re2f, lnIe2f, b2f, bnf, cnf, nbpf, bl2nf;
     };
     static constexpr int NS = 7, IQ = 5, ITH = 6, IS0 = 3, IS1 = -1;
@@ -346,6 +402,9 @@ struct Sersic {
         k.b = b;
         k.inv2n = 0.5 / n;
         k.lnre2 = 2.0 * lnre;
+        k.lnIe2 = lnIe * kLog2e;
+        k.b2 = b * kLog2e;
+        k.l2re2 = 2.0 * lnre * kLog2e;
         k.lnIe2f = (float)(lnIe * kLog2e);
         k.bf = (float)b;
         k.b2f = (float)(b * kLog2e);
@@ -363,12 +422,12 @@ struct Sersic {
         Pt<F64> p = frame<F64>(k.g, dx, dy);
         float I, z, L2;
         if constexpr (F64) {
-            double L = log(p.r2) - k.lnre2;                  // ln(r^2 / r_e^2)
-            double zd = exp(L * k.inv2n);                    // (r / r_e)^(1/n)
-            I64 = exp(k.lnIe - k.b * (zd - 1.0));
+            const double L2d = log2_pt(p.r2) - k.l2re2;      // log2(r^2 / r_e^2)
+            const double zd = exp2_pt(L2d * k.inv2n);        // (r / r_e)^(1/n)
+            I64 = exp2_pt(k.lnIe2 - k.b2 * (zd - 1.0));
             I = (float)I64;
             z = (float)zd;
-            L2 = (float)(L * kLog2e);
+            L2 = (float)L2d;
         } else {
             L2 = __log2f(p.r2f) - k.l2re2f;
             z = exp2f(L2 * k.inv2nf);

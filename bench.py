@@ -776,8 +776,9 @@ def main():
     sched = (tune.apply(gm, db, sample=n if args.tune_sample < 0 else args.tune_sample, trials=0)
              if args.tune_sample != 0 else None)
     if sched:
-        log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']} "
-            f"(tuned in {time.perf_counter() - t0:.1f} s: {[(t['plane_groups'], t['wg_per_cu'], round(t['ms'], 1)) for t in sched['trials']]})")
+        log(f"schedule {sched['key']}: plane groups {sched['plane_groups']}, workgroups/CU {sched['wg_per_cu']}, "
+            f"team {sched['team']} (min tiles {sched['team_min_tiles']}) (tuned in {time.perf_counter() - t0:.1f} s: "
+            f"{[(t['plane_groups'], t['wg_per_cu'], t['team'], round(t['ms'], 1)) for t in sched['trials']]})")
     p = gm.p
     # planes convolved per evaluation: the light and one per variable except sky and, for
     # one-component models, the magnitude whose derivative follows from the light
@@ -910,8 +911,10 @@ def main():
                      "flops_per_step": head["flops"]},
         "lm": {k: v for k, v in head.items() if k not in ("value", "ms_per_step", "achieved", "flops", "kernel")},
         "schedule": (None if not sched else
-                     {"plane_groups": sched["plane_groups"], "wg_per_cu": sched["wg_per_cu"], "key": sched["key"],
-                      "trials_ms": {f"g{t['plane_groups']}w{t['wg_per_cu']}": t["ms"] for t in sched["trials"]},
+                     {"plane_groups": sched["plane_groups"], "wg_per_cu": sched["wg_per_cu"], "team": sched["team"],
+                      "team_min_tiles": sched["team_min_tiles"], "key": sched["key"],
+                      "trials_ms": {f"g{t['plane_groups']}w{t['wg_per_cu']}t{t['team']}": t["ms"]
+                                    for t in sched["trials"]},
                       "sample": sched["sample"]}),
         "cpu_baseline": cpu,
         "parity": parity,

@@ -13,6 +13,12 @@ where the largest fits that need the most trials finish last and run at half
 speed when two workgroups share a CU).  Results are cached in a JSON file keyed by
 (device architecture, family, PSF side, parameter count, cutout-size bucket),
 so later runs apply a known schedule without timing.
+
+A second stage then tries workgroups per fit (gm_schedule.team) on top of the
+best plane-group count and residency: one workgroup per fit when the sample
+is small enough for the automatic teams to form, and teams of 2 or 4 for the
+fits of at least 16 tiles (128 x 128 px) when the batch has such cutouts, so
+that the largest fits of an uneven batch end sooner.
 """
 from __future__ import annotations
 
@@ -83,9 +89,22 @@ def tune(model: G.Model, batch: G.Batch, sample: int = 4096, reps: int = 3, tria
     for ng in G.gm_schedule_options(model, k if k else int(batch.psf_k.max())):
         for wpc in (0, 1):
             G.gm_set_schedule(model, k, ng, wpc, ctx=ctx)
-            results.append(dict(plane_groups=ng, wg_per_cu=wpc, ms=_time_fit(model, sb, start, ctx, reps, trials)))
+            results.append(dict(plane_groups=ng, wg_per_cu=wpc, team=0, team_min_tiles=0,
+                                ms=_time_fit(model, sb, start, ctx, reps, trials)))
     best = min(results, key=lambda t: t["ms"])
-    G.gm_set_schedule(model, k, best["plane_groups"], best["wg_per_cu"], ctx=ctx)
+    tiles = ((sb.h.astype(np.int64) + 31) // 32) * ((sb.w.astype(np.int64) + 31) // 32)
+    teams = []
+    if sb.n <= 2048:
+        teams.append((1, 0))
+    if (tiles >= 16).any():
+        teams += [(2, 16), (4, 16)]
+    for team, tmin in teams:
+        G.gm_set_schedule(model, k, best["plane_groups"], best["wg_per_cu"], team=team, team_min_tiles=tmin, ctx=ctx)
+        results.append(dict(plane_groups=best["plane_groups"], wg_per_cu=best["wg_per_cu"], team=team,
+                            team_min_tiles=tmin, ms=_time_fit(model, sb, start, ctx, reps, trials)))
+    best = min(results, key=lambda t: t["ms"])
+    G.gm_set_schedule(model, k, best["plane_groups"], best["wg_per_cu"], team=best["team"],
+                      team_min_tiles=best["team_min_tiles"], ctx=ctx)
     return dict(best, trials=results, sample=sb.n, trials_per_galaxy=trials)
 
 
@@ -112,10 +131,11 @@ def apply(model: G.Model, batch: G.Batch, cache_path: Optional[str] = None, samp
     cache = load(cache_path) if cache_path else {}
     if key in cache:
         e = cache[key]
-        G.gm_set_schedule(model, batch_psf_side(batch), e["plane_groups"], e["wg_per_cu"], ctx=ctx)
+        G.gm_set_schedule(model, batch_psf_side(batch), e["plane_groups"], e["wg_per_cu"], team=e.get("team", 0),
+                          team_min_tiles=e.get("team_min_tiles", 0), ctx=ctx)
         return dict(e, key=key, cached=True)
     res = tune(model, batch, sample=sample, trials=trials, ctx=ctx)
     if cache_path:
-        cache[key] = {k: res[k] for k in ("plane_groups", "wg_per_cu", "ms")}
+        cache[key] = {k: res[k] for k in ("plane_groups", "wg_per_cu", "team", "team_min_tiles", "ms")}
         save(cache_path, cache)
     return dict(res, key=key, cached=False)

@@ -64,9 +64,12 @@ def test_tuner_applies_and_caches(tmp_path):
     ctx = G.Context()
     path = str(tmp_path / "tune.json")
     r1 = T.apply(gm, db, cache_path=path, sample=64, ctx=ctx)
-    assert not r1["cached"] and len(r1["trials"]) == 2 * len(G.gm_schedule_options(gm, 15))
+    # plane groups x residency, then workgroups per fit (one each: the 64-galaxy sample forms teams by default)
+    assert not r1["cached"] and len(r1["trials"]) == 2 * len(G.gm_schedule_options(gm, 15)) + 1
+    assert {t["team"] for t in r1["trials"]} == {0, 1}
     cache = json.load(open(path))
     assert r1["key"] in cache and cache[r1["key"]]["plane_groups"] == r1["plane_groups"]
+    assert cache[r1["key"]]["team"] == r1["team"]
     r2 = T.apply(gm, db, cache_path=path, ctx=ctx)
     assert r2["cached"] and r2["plane_groups"] == r1["plane_groups"]
     print(f"tuned {r1['key']}: {r1['trials']}", flush=True)

@@ -348,9 +348,10 @@ __device__ inline void row_part(const T *rp, const cfloat *pr, T &a0, T &a1, T &
 }
 
 // Convolve one plane (elements of type T, row pitch IWP) for a 1 x 4 output
-// strip with a compile-time PSF side.  Up to side 15, FP32 planes load the
-// segment of the next PSF row while the current one is used and the FP64
-// plane, whose segment is twice as large, loads one row at a time.  Wider
+// strip with a compile-time PSF side (the Adam fit's planes).  Up to side 15,
+// FP32 planes load the segment of the next PSF row while the current one is
+// used and the FP64 plane, whose segment is twice as large, loads one row at
+// a time.  Wider
 // PSFs take each row in two halves of taps, each with only the part of the
 // segment it reads, so that the kernel fits two workgroups' registers.
 template <int KT, typename T>
@@ -410,6 +411,67 @@ __device__ inline void conv_plane_any(const T *base, int r, int K, int IWP, cons
     out[0] = a0; out[1] = a1; out[2] = a2; out[3] = a3;
 }
 
+// Compile-time PSF sides: the planes of a group row by row of the PSF, every
+// plane of the group under one row's taps.  A row's taps are scalar loads,
+// which complete out of order with the LDS reads of the segments: with them
+// loaded once per PSF row, no scalar load is outstanding while the planes of
+// the row run, so the segment reads of the next plane overlap the products of
+// the current one.  Each accumulator sees the products in the order of the
+// plane-by-plane loop (rows, then taps).
+template <class F, int KT, int LO, int HI>
+__device__ inline void conv_group_rows(const float *__restrict__ buf, const cfloat *psf, int r, int cg,
+                                       double (&acc0)[4], float (&acc)[F::NPL][4])
+{
+    constexpr int IH = TILE + KT - 1, IWP = (28 + 4 * ((KT + 3 + 3) / 4));
+    constexpr int plane_sz = IH * IWP;
+    constexpr int QLO = LO == 0 ? 1 : LO;
+    constexpr int SEG32 = ((KT + 3 + 3) / 4) * 4, SEG64 = ((KT + 3 + 1) / 2) * 2;
+    const float *bf = ((LO == 0) ? buf + 2 * plane_sz : buf) + 4 * cg;
+    const double *b64 = reinterpret_cast<const double *>(buf) + 4 * cg;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    float a[HI - QLO][4];
+#pragma unroll
+    for (int pl = 0; pl < HI - QLO; ++pl) a[pl][0] = a[pl][1] = a[pl][2] = a[pl][3] = 0.0f;
+#pragma unroll 1
+    for (int u = 0; u < KT; ++u) {
+        const int ro = (r + KT - 1 - u) * IWP;
+        const cfloat *pr = psf + u * KT;
+        if constexpr (KT > 15) {
+            // wide PSFs: each row in two halves of taps, each with only the part
+            // of the segment it reads (taps v < VS read elements from ES on)
+            constexpr int ES = 4 * ((KT - 1) / 8), VS = KT - ES;
+            if constexpr (LO == 0) {
+                row_part<KT, 0, VS, ES>(b64 + ro, pr, d0, d1, d2, d3);
+                row_part<KT, VS, KT, 0>(b64 + ro, pr, d0, d1, d2, d3);
+            }
+#pragma unroll
+            for (int pl = 0; pl < HI - QLO; ++pl) {
+                row_part<KT, 0, VS, ES>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+                row_part<KT, VS, KT, 0>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+            }
+        } else {
+            if constexpr (LO == 0) {
+                double seg[SEG64];
+                load_seg<KT>(b64 + ro, seg);
+                row_fma<KT>(seg, pr, d0, d1, d2, d3);
+            }
+#pragma unroll
+            for (int pl = 0; pl < HI - QLO; ++pl) {
+                float seg[SEG32];
+                load_seg<KT>(bf + pl * plane_sz + ro, seg);
+                row_fma<KT>(seg, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+            }
+        }
+    }
+    if constexpr (LO == 0) {
+        acc0[0] = d0; acc0[1] = d1; acc0[2] = d2; acc0[3] = d3;
+    }
+#pragma unroll
+    for (int pl = QLO; pl < HI; ++pl)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[pl][t] = a[pl - QLO][t];
+}
+
 // Convolve planes LO..HI-1 for this thread's 1 x 4 output strip (tile row r,
 // columns 4 cg .. 4 cg + 3): plane 0 in FP64, the derivative planes in FP32.
 // KT > 0: compile-time PSF side; 0: any K.
@@ -417,20 +479,17 @@ template <class F, int KT, int LO, int HI>
 __device__ inline void conv_group(const float *__restrict__ buf, int K, const cfloat *psf, int r, int cg,
                                   double (&acc0)[4], float (&acc)[F::NPL][4])
 {
-    const int IH = region_h(K), IWP = region_wp(K);
-    const int plane_sz = IH * IWP;
-    constexpr int QLO = LO == 0 ? 1 : LO;
-    const float *bf = (LO == 0) ? buf + 2 * plane_sz : buf;
-    if constexpr (LO == 0) {
-        const double *base = reinterpret_cast<const double *>(buf) + 4 * cg;
-        if constexpr (KT > 0) conv_plane<KT, double>(base, r, IWP, psf, acc0);
-        else conv_plane_any<double>(base, r, K, IWP, psf, acc0);
-    }
+    if constexpr (KT > 0) {
+        conv_group_rows<F, KT, LO, HI>(buf, psf, r, cg, acc0, acc);
+    } else {
+        const int IH = region_h(K), IWP = region_wp(K);
+        const int plane_sz = IH * IWP;
+        constexpr int QLO = LO == 0 ? 1 : LO;
+        const float *bf = (LO == 0) ? buf + 2 * plane_sz : buf;
+        if constexpr (LO == 0)
+            conv_plane_any<double>(reinterpret_cast<const double *>(buf) + 4 * cg, r, K, IWP, psf, acc0);
 #pragma unroll
-    for (int pl = QLO; pl < HI; ++pl) {
-        const float *base = bf + (pl - QLO) * plane_sz + 4 * cg;
-        if constexpr (KT > 0) conv_plane<KT, float>(base, r, IWP, psf, acc[pl]);
-        else conv_plane_any<float>(base, r, K, IWP, psf, acc[pl]);
+        for (int pl = QLO; pl < HI; ++pl) conv_plane_any<float>(bf + (pl - QLO) * plane_sz + 4 * cg, r, K, IWP, psf, acc[pl]);
     }
 }
 

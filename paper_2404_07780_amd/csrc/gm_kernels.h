@@ -139,6 +139,41 @@ __host__ __device__ constexpr size_t window_scratch_bytes()
     return (size_t)MAXWIN * MAXOSF * (sizeof(double) + F::ND * sizeof(float));
 }
 
+// Dynamic LDS of the evaluating kernels: the plane buffer (which also hosts
+// the window partial sums, the wave partial sums of the normal equations and
+// the thread-0 solver temporaries), then a copy of the galaxy's PSF with rows
+// padded to psf_pitch floats (16-byte aligned rows).
+__host__ __device__ inline int psf_pitch(int K) { return (K + 3) & ~3; }
+template <class F, int NG>
+__host__ __device__ inline size_t lds_main_bytes(int K)
+{
+    size_t m = planes_bytes<F, NG>(K);
+    const size_t sums = (size_t)NWAVE * (1 + F::P + F::P * (F::P + 1) / 2) * 8, solve = (size_t)3 * F::P * F::P * 8;
+    m = m > sums ? m : sums;
+    m = m > solve ? m : solve;
+    m = m > window_scratch_bytes<F>() ? m : window_scratch_bytes<F>();
+    return (m + 15) & ~(size_t)15;
+}
+template <class F, int NG>
+__host__ __device__ inline size_t lds_total_bytes(int K)
+{
+    return lds_main_bytes<F, NG>(K) + (size_t)K * psf_pitch(K) * sizeof(float);
+}
+
+// Copy the PSF (K x K, global) into its LDS rows; the caller's next barrier
+// publishes it.
+template <class F, int NG>
+__device__ inline const float *stage_psf(float *planes, const float *psf, int K)
+{
+    float *d = planes + lds_main_bytes<F, NG>(K) / sizeof(float);
+    const int kp = psf_pitch(K);
+    for (int i = threadIdx.x; i < K * K; i += NT) {
+        const int u = i / K;
+        d[u * kp + (i - u * K)] = psf[i];
+    }
+    return d;
+}
+
 // Scalar prologue (wave 0) + oversampled window tables (all threads).
 // u: LDS (FP64, internal).  scratch: the idle plane buffer.
 template <class F>
@@ -286,8 +321,8 @@ __device__ inline int64_t uniform64(int64_t x)
 }
 
 // One PSF row (KT taps) against a row segment: acc[t] += sum_v p[v] seg[t + KT-1-v].
-template <int KT, typename T>
-__device__ inline void row_fma(const T *seg, const cfloat *pr, T &a0, T &a1, T &a2, T &a3)
+template <int KT, typename T, typename PR>
+__device__ inline void row_fma(const T *seg, PR pr, T &a0, T &a1, T &a2, T &a3)
 {
 #pragma unroll
     for (int v = 0; v < KT; ++v) {
@@ -320,8 +355,8 @@ __device__ inline void load_seg(const T *p, T *seg)
 
 // Taps v0 .. v1-1 of one PSF row against the segment elements e0 .. (e0 a
 // multiple of the 16-byte vector width): acc[t] += sum_v p[v] seg[KT-1-v+t].
-template <int KT, int V0, int V1, int E0, typename T>
-__device__ inline void row_part(const T *rp, const cfloat *pr, T &a0, T &a1, T &a2, T &a3)
+template <int KT, int V0, int V1, int E0, typename T, typename PR>
+__device__ inline void row_part(const T *rp, PR pr, T &a0, T &a1, T &a2, T &a3)
 {
     constexpr int PER = 16 / sizeof(T);
     constexpr int N = ((KT + 2 - V0) - E0 + 1 + PER - 1) / PER * PER;
@@ -411,7 +446,19 @@ __device__ inline void conv_plane_any(const T *base, int r, int K, int IWP, cons
     out[0] = a0; out[1] = a1; out[2] = a2; out[3] = a3;
 }
 
-// Compile-time PSF sides: the planes of a group row by row of the PSF, every
+// The taps of PSF row u from its LDS copy (rows of KP = psf_pitch floats).
+template <int KP>
+__device__ inline void load_taps(const float *psl, int u, float (&tp)[KP])
+{
+    const float4 *tv = reinterpret_cast<const float4 *>(psl + u * KP);
+#pragma unroll
+    for (int q = 0; q < KP / 4; ++q) {
+        const float4 t = tv[q];
+        tp[4 * q] = t.x; tp[4 * q + 1] = t.y; tp[4 * q + 2] = t.z; tp[4 * q + 3] = t.w;
+    }
+}
+
+// PSF sides above 15: the planes of a group row by row of the PSF, every
 // plane of the group under one row's taps.  A row's taps are scalar loads,
 // which complete out of order with the LDS reads of the segments: with them
 // loaded once per PSF row, no scalar load is outstanding while the planes of
@@ -419,13 +466,12 @@ __device__ inline void conv_plane_any(const T *base, int r, int K, int IWP, cons
 // the current one.  Each accumulator sees the products in the order of the
 // plane-by-plane loop (rows, then taps).
 template <class F, int KT, int LO, int HI>
-__device__ inline void conv_group_rows(const float *__restrict__ buf, const cfloat *psf, int r, int cg,
+__device__ inline void conv_group_wide(const float *__restrict__ buf, const cfloat *psf, int r, int cg,
                                        double (&acc0)[4], float (&acc)[F::NPL][4])
 {
     constexpr int IH = TILE + KT - 1, IWP = (28 + 4 * ((KT + 3 + 3) / 4));
     constexpr int plane_sz = IH * IWP;
     constexpr int QLO = LO == 0 ? 1 : LO;
-    constexpr int SEG32 = ((KT + 3 + 3) / 4) * 4, SEG64 = ((KT + 3 + 1) / 2) * 2;
     const float *bf = ((LO == 0) ? buf + 2 * plane_sz : buf) + 4 * cg;
     const double *b64 = reinterpret_cast<const double *>(buf) + 4 * cg;
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
@@ -436,31 +482,17 @@ __device__ inline void conv_group_rows(const float *__restrict__ buf, const cflo
     for (int u = 0; u < KT; ++u) {
         const int ro = (r + KT - 1 - u) * IWP;
         const cfloat *pr = psf + u * KT;
-        if constexpr (KT > 15) {
-            // wide PSFs: each row in two halves of taps, each with only the part
-            // of the segment it reads (taps v < VS read elements from ES on)
-            constexpr int ES = 4 * ((KT - 1) / 8), VS = KT - ES;
-            if constexpr (LO == 0) {
-                row_part<KT, 0, VS, ES>(b64 + ro, pr, d0, d1, d2, d3);
-                row_part<KT, VS, KT, 0>(b64 + ro, pr, d0, d1, d2, d3);
-            }
+        // wide PSFs: each row in two halves of taps, each with only the part
+        // of the segment it reads (taps v < VS read elements from ES on)
+        constexpr int ES = 4 * ((KT - 1) / 8), VS = KT - ES;
+        if constexpr (LO == 0) {
+            row_part<KT, 0, VS, ES>(b64 + ro, pr, d0, d1, d2, d3);
+            row_part<KT, VS, KT, 0>(b64 + ro, pr, d0, d1, d2, d3);
+        }
 #pragma unroll
-            for (int pl = 0; pl < HI - QLO; ++pl) {
-                row_part<KT, 0, VS, ES>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
-                row_part<KT, VS, KT, 0>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
-            }
-        } else {
-            if constexpr (LO == 0) {
-                double seg[SEG64];
-                load_seg<KT>(b64 + ro, seg);
-                row_fma<KT>(seg, pr, d0, d1, d2, d3);
-            }
-#pragma unroll
-            for (int pl = 0; pl < HI - QLO; ++pl) {
-                float seg[SEG32];
-                load_seg<KT>(bf + pl * plane_sz + ro, seg);
-                row_fma<KT>(seg, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
-            }
+        for (int pl = 0; pl < HI - QLO; ++pl) {
+            row_part<KT, 0, VS, ES>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+            row_part<KT, VS, KT, 0>(bf + pl * plane_sz + ro, pr, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
         }
     }
     if constexpr (LO == 0) {
@@ -472,15 +504,82 @@ __device__ inline void conv_group_rows(const float *__restrict__ buf, const cflo
         for (int t = 0; t < 4; ++t) acc[pl][t] = a[pl - QLO][t];
 }
 
+// PSF sides up to 15.  Every load of the loops is an LDS read (the taps
+// from the PSF's LDS copy, the segments from the planes), and LDS reads
+// complete in order, so a wait covers exactly the reads a product needs and
+// the reads issued after them stay in flight.  The FP64 plane runs first, on
+// its own, with the segment and taps of the next PSF row loaded while the
+// current row is used; then the FP32 planes, row by row of the PSF with every
+// plane under the row's taps, each plane's segment loaded while the previous
+// plane's products run.  Each accumulator sees the products in the same order
+// (rows, then taps).
+template <class F, int KT, int LO, int HI>
+__device__ inline void conv_group_rows(const float *__restrict__ buf, const float *__restrict__ psl, int r, int cg,
+                                       double (&acc0)[4], float (&acc)[F::NPL][4])
+{
+    constexpr int KP = (KT + 3) & ~3;
+    constexpr int IH = TILE + KT - 1, IWP = (28 + 4 * ((KT + 3 + 3) / 4));
+    constexpr int plane_sz = IH * IWP;
+    constexpr int QLO = LO == 0 ? 1 : LO, NP = HI - QLO;
+    constexpr int SEG32 = ((KT + 3 + 3) / 4) * 4, SEG64 = ((KT + 3 + 1) / 2) * 2;
+    const float *bf = ((LO == 0) ? buf + 2 * plane_sz : buf) + 4 * cg;
+    const float *rowp = bf + (r + KT - 1) * IWP;          // row of PSF row 0; PSF row u is -u * IWP
+    if constexpr (LO == 0) {
+        const double *b64 = reinterpret_cast<const double *>(buf) + 4 * cg + (r + KT - 1) * IWP;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        double sa[SEG64], sb[SEG64];
+        float ta[KP], tb[KP];
+        load_taps<KP>(psl, 0, ta);
+        load_seg<KT>(b64, sa);
+#pragma unroll 1
+        for (int u = 0; u + 1 < KT; u += 2) {
+            load_taps<KP>(psl, u + 1, tb);
+            load_seg<KT>(b64 - (u + 1) * IWP, sb);
+            row_fma<KT>(sa, ta, d0, d1, d2, d3);
+            if (u + 2 < KT) {
+                load_taps<KP>(psl, u + 2, ta);
+                load_seg<KT>(b64 - (u + 2) * IWP, sa);
+            }
+            row_fma<KT>(sb, tb, d0, d1, d2, d3);
+        }
+        if (KT & 1) row_fma<KT>(sa, ta, d0, d1, d2, d3);
+        acc0[0] = d0; acc0[1] = d1; acc0[2] = d2; acc0[3] = d3;
+    }
+    float a[NP > 0 ? NP : 1][4];
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl) a[pl][0] = a[pl][1] = a[pl][2] = a[pl][3] = 0.0f;
+    if constexpr (NP > 0) {
+#pragma unroll 1
+        for (int u = 0; u < KT; ++u) {
+            float tp[KP];
+            load_taps<KP>(psl, u, tp);
+            const float *ro = rowp - u * IWP;
+            float sg[2][SEG32];
+            load_seg<KT>(ro, sg[0]);
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) {
+                if (pl + 1 < NP) load_seg<KT>(ro + (pl + 1) * plane_sz, sg[(pl + 1) & 1]);
+                row_fma<KT>(sg[pl & 1], tp, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+            }
+        }
+    }
+#pragma unroll
+    for (int pl = QLO; pl < HI; ++pl)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[pl][t] = a[pl - QLO][t];
+}
+
 // Convolve planes LO..HI-1 for this thread's 1 x 4 output strip (tile row r,
 // columns 4 cg .. 4 cg + 3): plane 0 in FP64, the derivative planes in FP32.
 // KT > 0: compile-time PSF side; 0: any K.
 template <class F, int KT, int LO, int HI>
-__device__ inline void conv_group(const float *__restrict__ buf, int K, const cfloat *psf, int r, int cg,
-                                  double (&acc0)[4], float (&acc)[F::NPL][4])
+__device__ inline void conv_group(const float *__restrict__ buf, int K, const cfloat *psf, const float *psl, int r,
+                                  int cg, double (&acc0)[4], float (&acc)[F::NPL][4])
 {
-    if constexpr (KT > 0) {
-        conv_group_rows<F, KT, LO, HI>(buf, psf, r, cg, acc0, acc);
+    if constexpr (KT > 15) {
+        conv_group_wide<F, KT, LO, HI>(buf, psf, r, cg, acc0, acc);
+    } else if constexpr (KT > 0) {
+        conv_group_rows<F, KT, LO, HI>(buf, psl, r, cg, acc0, acc);
     } else {
         const int IH = region_h(K), IWP = region_wp(K);
         const int plane_sz = IH * IWP;
@@ -496,15 +595,16 @@ __device__ inline void conv_group(const float *__restrict__ buf, int K, const cf
 // All groups of one tile: fill, convolve, leave the buffer idle.
 template <class F, int KT, int NG, int G = 0>
 __device__ inline void tile_planes(const EvalShared<F> &sh, float *buf, int H, int W, int K, int ti0, int tj0,
-                                   const cfloat *psf, int r, int cg, double (&acc0)[4], float (&acc)[F::NPL][4])
+                                   const cfloat *psf, const float *psl, int r, int cg, double (&acc0)[4],
+                                   float (&acc)[F::NPL][4])
 {
     if constexpr (G < NG) {
         constexpr int LO = group_bound(F::NPL, NG, G), HI = group_bound(F::NPL, NG, G + 1);
         fill_region<F, LO, HI>(sh, buf, H, W, K, ti0, tj0);
         __syncthreads();
-        conv_group<F, KT, LO, HI>(buf, K, psf, r, cg, acc0, acc);
+        conv_group<F, KT, LO, HI>(buf, K, psf, psl, r, cg, acc0, acc);
         __syncthreads();
-        tile_planes<F, KT, NG, G + 1>(sh, buf, H, W, K, ti0, tj0, psf, r, cg, acc0, acc);
+        tile_planes<F, KT, NG, G + 1>(sh, buf, H, W, K, ti0, tj0, psf, psl, r, cg, acc0, acc);
     }
 }
 
@@ -569,6 +669,7 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
     constexpr int NR = 1 + P + P * (P + 1) / 2;
     const int H = me.h, W = me.w, K = me.k;
     const int tid = threadIdx.x;
+    const float *psl = stage_psf<F, NG>(planes, ba.psf + uniform64(me.psf_off), K);
     eval_prologue<F>(u, ma, H, W, sh, planes);
     const cfloat *psf = (const cfloat *)(ba.psf + uniform64(me.psf_off));
     // Per-thread partial sums: chi^2 in FP64 (it decides accept/reject), g and
@@ -604,7 +705,7 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
             const int ti0 = ty * TILE, tj0 = tx * TILE;
             double acc0[4];
             float acc[F::NPL][4];
-            tile_planes<F, KT, NG>(sh, planes, H, W, K, ti0, tj0, psf, r, cg, acc0, acc);
+            tile_planes<F, KT, NG>(sh, planes, H, W, K, ti0, tj0, psf, psl, r, cg, acc0, acc);
             const int i = ti0 + r;
             if (i < H) {
                 float bw[4] = {1.0f, 1.0f, 1.0f, 1.0f};
@@ -1575,6 +1676,7 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
                 sfree[k] = c >= 0;
             }
         }
+        const float *psl = stage_psf<F, NG>(planes, ba.psf + uniform64(me.psf_off), K);
         __syncthreads();
         eval_prologue<F>(su, ma, H, W, esh, planes);
         const int ti0 = ti.ty * TILE, tj0 = ti.tx * TILE;
@@ -1582,8 +1684,8 @@ __global__ __launch_bounds__(NT) void image_kernel(ModelArgs ma, BatchArgs ba, I
         strip_of(tid, K, r, cg);
         double acc0[4];
         float acc[F::NPL][4];
-        tile_planes<F, KT, NG>(esh, planes, H, W, K, ti0, tj0, (const cfloat *)(ba.psf + uniform64(me.psf_off)), r,
-                               cg, acc0, acc);
+        tile_planes<F, KT, NG>(esh, planes, H, W, K, ti0, tj0, (const cfloat *)(ba.psf + uniform64(me.psf_off)), psl,
+                               r, cg, acc0, acc);
         const int i = ti0 + r;
         double v[P];
 #pragma unroll

@@ -132,14 +132,11 @@ size_t static_lds()
     return sizeof(EvalShared<F>) + sizeof(LMShared<F>) + 64;
 }
 
-// Dynamic LDS for NG plane groups and PSF side K: the plane buffer, which also
-// hosts the window partial sums, the wave partial sums of the normal
-// equations and the thread-0 solver temporaries.
+// Dynamic LDS for NG plane groups and PSF side K (lds_total_bytes).
 template <class F, int NG>
 size_t lds_bytes(int K)
 {
-    return std::max({planes_bytes<F, NG>(K), (size_t)NWAVE * (1 + F::P + F::P * (F::P + 1) / 2) * 8,
-                     (size_t)3 * F::P * F::P * 8, window_scratch_bytes<F>()});
+    return lds_total_bytes<F, NG>(K);
 }
 
 template <typename Kern>

@@ -556,10 +556,16 @@ __device__ inline void conv_group_rows(const float *__restrict__ buf, const floa
             const float *ro = rowp - u * IWP;
             float sg[2][SEG32];
             load_seg<KT>(ro, sg[0]);
+            constexpr int NRD = (KT + 3 + 3) / 4;      // 16-byte reads per segment
+            __builtin_amdgcn_sched_group_barrier(0x100, KP / 4 + NRD, 0);
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) {
-                if (pl + 1 < NP) load_seg<KT>(ro + (pl + 1) * plane_sz, sg[(pl + 1) & 1]);
+                if (pl + 1 < NP) {
+                    load_seg<KT>(ro + (pl + 1) * plane_sz, sg[(pl + 1) & 1]);
+                    __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
+                }
                 row_fma<KT>(sg[pl & 1], tp, a[pl][0], a[pl][1], a[pl][2], a[pl][3]);
+                __builtin_amdgcn_sched_group_barrier(0x002, 4 * KT, 0);
             }
         }
     }

@@ -203,8 +203,9 @@ __device__ inline void gammainc_wave(double a, double x, double lga1, double psi
 // the error after a Newton step, about |f''/(2 f')| step^2 with
 // f''/f' = (a - 1)/b - 1, is below 1e-16 b (or a step is below 1e-14 b);
 // db/dn by implicit differentiation, -2 (dP/da) / (dP/dx).  All lanes of
-// one wave.
-__device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
+// one wave.  Also returns ln Gamma(2n) and psi(2n) (= psi(2n + 1) - 1/(2n)),
+// which the solve computes on the way.
+__device__ inline double sersic_b_wave(double n, int lane, double *dbdn, double *lg2n, double *psi2n)
 {
     double a = 2.0 * n, lo = 0.0, hi = a + 20.0;
     double in = 1.0 / n;
@@ -227,8 +228,11 @@ __device__ inline double sersic_b_wave(double n, int lane, double *dbdn)
         if (st < 1e-14 * b || (newton && pred < 1e-16 * b)) break;
     }
     double P, dPa;
-    gammainc_wave(a, b, lga1, digamma(a + 1.0), lane, true, &P, &dPa);
+    const double psi1 = digamma(a + 1.0);
+    gammainc_wave(a, b, lga1, psi1, lane, true, &P, &dPa);
     *dbdn = -2.0 * dPa / exp((a - 1.0) * log(b) - b - lga);
+    *lg2n = lga;
+    *psi2n = psi1 - 1.0 / a;
     return b;
 }
 
@@ -392,11 +396,9 @@ struct Sersic {
     {
         double x0 = u[0], y0 = u[1], m = u[2], lnre = u[3], lnn = u[4], q = u[5], th = u[6];
         double n = exp(lnn);
-        double bp;
-        double b = sersic_b_wave(n, lane, &bp);
-        double psi = digamma(2.0 * n);
-        double lnIe = -0.4 * kLn10 * (m - m0) + 2.0 * n * log(b) - log(2.0 * kPi * q * n) - 2.0 * lnre
-                      - lgamma(2.0 * n) - b;
+        double bp, lg2n, psi;
+        double b = sersic_b_wave(n, lane, &bp, &lg2n, &psi);
+        double lnIe = -0.4 * kLn10 * (m - m0) + 2.0 * n * log(b) - log(2.0 * kPi * q * n) - 2.0 * lnre - lg2n - b;
         geo_prep(x0, y0, q, th, H, W, osf, osw, k.g);
         k.lnIe = lnIe;
         k.b = b;

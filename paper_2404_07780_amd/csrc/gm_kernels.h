@@ -63,10 +63,21 @@ struct BatchArgs {
 __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Input-region geometry of a tile for PSF side K (row pitch IWP in elements).
-__host__ __device__ inline int region_h(int K) { return TILE + K - 1; }
+__host__ __device__ constexpr int region_h(int K) { return TILE + K - 1; }
 // Row pitch: the 32 outputs' 16-byte-aligned input segments need
 // 28 + 4 ceil((K + 3) / 4) floats.
-__host__ __device__ inline int region_wp(int K) { return 28 + 4 * ((K + 3 + 3) / 4); }
+__host__ __device__ constexpr int region_wp(int K) { return 28 + 4 * ((K + 3 + 3) / 4); }
+
+// FP64 light plane rows: with a pitch of 48 doubles (PSF side 15) the 16-byte
+// reads of two adjacent rows (one 16-lane group) fall on the same LDS banks;
+// odd rows stored 2 doubles (16 bytes) further on read conflict-free
+// (measured with the bank-conflict counter).  The pitch has the 2 spare
+// doubles this needs.
+template <int KT>
+__host__ __device__ constexpr bool shift64()
+{
+    return KT > 0 && region_wp(KT) == 48 && region_h(KT) + 2 <= 48;
+}
 
 // Output strip of thread tid in a tile: row r, columns 4 cg .. 4 cg + 3.  Wave
 // w covers rows 8w .. 8w + 7, 8 lanes per row.  When the row pitch is 8
@@ -268,7 +279,7 @@ __device__ inline void planes_at(const EvalShared<F> &sh, int i, int j, int H, d
 // then the FP32 planes in order.  Region points outside the image are the
 // convolution's zero padding; the points inside form a rectangle whose
 // profile values are spread linearly over all threads of the workgroup.
-template <class F, int LO, int HI>
+template <class F, int LO, int HI, bool SH = false>
 __device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, int K, int ti0, int tj0)
 {
     const int IH = region_h(K), IWP = region_wp(K), IW = TILE + K - 1, c = (K - 1) / 2;
@@ -279,8 +290,10 @@ __device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, i
     // region rows r0..r1-1 and columns c0..c1-1 lie inside the image
     const int r0 = max(0, c - ti0), r1 = min(IH, H + c - ti0);
     const int c0 = max(0, c - tj0), c1 = min(IW, W + c - tj0);
-    auto store = [&](int idx, double v0, const float *dp) {
-        if constexpr (LO == 0) b0[idx] = v0;
+    // region point (ri, ci); SH: odd rows of the FP64 plane 2 further on
+    auto store = [&](int ri, int ci, double v0, const float *dp) {
+        const int idx = ri * IWP + ci;
+        if constexpr (LO == 0) b0[SH ? idx + 2 * (ri & 1) : idx] = v0;
 #pragma unroll
         for (int q = QLO; q < HI; ++q) bf[(q - QLO) * plane_sz + idx] = dp[q - 1];
     };
@@ -291,7 +304,7 @@ __device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, i
         for (int q = 0; q < F::NPL - 1; ++q) z[q] = 0.0f;
         for (int t = threadIdx.x; t < IH * IW; t += NT) {
             const int ri = t / IW, ci = t - ri * IW;
-            if (ri < r0 || ri >= r1 || ci < c0 || ci >= c1) store(ri * IWP + ci, 0.0, z);
+            if (ri < r0 || ri >= r1 || ci < c0 || ci >= c1) store(ri, ci, 0.0, z);
         }
     }
     const int nc = c1 - c0, npts = (r1 - r0) * nc;
@@ -304,7 +317,7 @@ __device__ void fill_region(const EvalShared<F> &sh, float *buf, int H, int W, i
         double v0;
         float dp[F::NPL - 1];
         planes_at<F, LO == 0>(sh, ti0 - c + ri, tj0 - c + ci, H, v0, dp);
-        store(ri * IWP + ci, v0, dp);
+        store(ri, ci, v0, dp);
     }
 }
 
@@ -525,20 +538,25 @@ __device__ inline void conv_group_rows(const float *__restrict__ buf, const floa
     const float *bf = ((LO == 0) ? buf + 2 * plane_sz : buf) + 4 * cg;
     const float *rowp = bf + (r + KT - 1) * IWP;          // row of PSF row 0; PSF row u is -u * IWP
     if constexpr (LO == 0) {
-        const double *b64 = reinterpret_cast<const double *>(buf) + 4 * cg + (r + KT - 1) * IWP;
+        // rows of even u start at pe - u IWP, of odd u at po - (u - 1) IWP (the
+        // row parity, and so the shift64 offset, alternates with u)
+        const int rr0 = r + KT - 1;
+        const double *b64 = reinterpret_cast<const double *>(buf) + 4 * cg;
+        const double *pe = b64 + rr0 * IWP + (shift64<KT>() ? 2 * (rr0 & 1) : 0);
+        const double *po = b64 + (rr0 - 1) * IWP + (shift64<KT>() ? 2 * ((rr0 - 1) & 1) : 0);
         double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
         double sa[SEG64], sb[SEG64];
         float ta[KP], tb[KP];
         load_taps<KP>(psl, 0, ta);
-        load_seg<KT>(b64, sa);
+        load_seg<KT>(pe, sa);
 #pragma unroll 1
         for (int u = 0; u + 1 < KT; u += 2) {
             load_taps<KP>(psl, u + 1, tb);
-            load_seg<KT>(b64 - (u + 1) * IWP, sb);
+            load_seg<KT>(po - u * IWP, sb);
             row_fma<KT>(sa, ta, d0, d1, d2, d3);
             if (u + 2 < KT) {
                 load_taps<KP>(psl, u + 2, ta);
-                load_seg<KT>(b64 - (u + 2) * IWP, sa);
+                load_seg<KT>(pe - (u + 2) * IWP, sa);
             }
             row_fma<KT>(sb, tb, d0, d1, d2, d3);
         }
@@ -606,7 +624,7 @@ __device__ inline void tile_planes(const EvalShared<F> &sh, float *buf, int H, i
 {
     if constexpr (G < NG) {
         constexpr int LO = group_bound(F::NPL, NG, G), HI = group_bound(F::NPL, NG, G + 1);
-        fill_region<F, LO, HI>(sh, buf, H, W, K, ti0, tj0);
+        fill_region<F, LO, HI, shift64<KT>()>(sh, buf, H, W, K, ti0, tj0);
         __syncthreads();
         conv_group<F, KT, LO, HI>(buf, K, psf, psl, r, cg, acc0, acc);
         __syncthreads();

@@ -168,7 +168,7 @@ struct AdamArgs {
 };
 
 template <class F, int KT, int NG>
-__global__ __launch_bounds__(NT, (min_wg<F, KT>())) void adam_fit_kernel(ModelArgs ma, BatchArgs ba, AdamArgs aa)
+__global__ __launch_bounds__(NT, (min_wg<F, KT, NG>())) void adam_fit_kernel(ModelArgs ma, BatchArgs ba, AdamArgs aa)
 {
     extern __shared__ float4 dyn_lds[];
     float *planes = reinterpret_cast<float *>(dyn_lds);

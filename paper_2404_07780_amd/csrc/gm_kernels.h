@@ -1413,11 +1413,19 @@ __device__ void load_u(LMShared<F> &s, const ModelArgs &ma, const double *params
 // spills inside loops (measured 1.38x faster Sersic fits at 64 x 64, PSF
 // side 15); the two-component models need more registers than that for
 // their accumulators and keep one (as does the error kernel, which would
-// spill inside its loops).
-template <class F, int KT>
+// spill inside its loops).  Where a workgroup's LDS (plane buffer, PSF
+// copies, static state) leaves room for one per CU only, the target is one
+// too: the second workgroup's registers could never be used, and the 256
+// VGPR cap made the wide-PSF kernels spill.
+template <class F, int KT, int NG>
 __host__ __device__ constexpr int min_wg()
 {
-    return F::NCOMP == 1 ? 2 : 1;
+    if (F::NCOMP != 1) return 1;
+    if (KT == 0) return 2;
+    const size_t planes = (size_t)max_group_units(F::NPL, NG) * region_h(KT) * region_wp(KT) * sizeof(float);
+    const size_t psf = (size_t)KT * ((KT + 3) & ~3) * (sizeof(float) + sizeof(double));
+    const size_t per_wg = planes + psf + sizeof(EvalShared<F>) + sizeof(LMShared<F>) + 1024;
+    return 2 * per_wg <= (size_t)160 * 1024 ? 2 : 1;
 }
 
 // Team steps around the one evaluation site of lm_fit_kernel.
@@ -1483,7 +1491,7 @@ __device__ inline bool team_collect(LMShared<F> &s, TeamCtl *ctl, const double *
 // the refit from refit_start); members follow the leader's commands.  The
 // model is evaluated at a single site for all three roles.
 template <class F, int KT, int NG>
-__global__ __launch_bounds__(NT, (min_wg<F, KT>())) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, FitArgs fa)
+__global__ __launch_bounds__(NT, (min_wg<F, KT, NG>())) void lm_fit_kernel(ModelArgs ma, BatchArgs ba, FitArgs fa)
 {
     extern __shared__ float4 dyn_lds[];
     float *planes = reinterpret_cast<float *>(dyn_lds);

@@ -156,7 +156,7 @@ def flops_per_eval(b: S.Batch, p: int, npl: int):
 
 
 def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi: int = 20, box: bool = False,
-                 shape: str = None):
+                 shape: str = None, lam: float = 1e-3):
     """FP64 oracle on galaxies 0..n_sample-1 of the workload (images rendered and
     noised on the host), all host cores, LM from its own moment start; the GPU
     fits of the same data (plain, and learned when a network is given) are
@@ -190,11 +190,12 @@ def cpu_baseline(cfg: str, n_sample: int, seed: int, gm: G.Model, mlp=None, pmi:
                     fails=fails[:8])
 
     start, _ = G.gm_default_guess(gm, db)
-    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start)]
+    gp, gc, gn, gs = [t.cpu().numpy() for t in G.gm_fit_batch(gm, db, start, lambda0=lam)]
     parity = dict(sample=n_sample, oracle_converged=int((rs == 0).sum()), oracle_mean_iters=float(rn.mean()),
                   plain=judge(gp, gc, gs))
     if mlp is not None:
-        lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=pmi)]
+        lp, lc, ln, ls, fb = [t.cpu().numpy() for t in G.gm_fit_learned(gm, db, mlp, proposal_max_iter=pmi,
+                                                                         lambda0=lam)]
         parity["learned"] = judge(lp, lc, ls)
         parity["learned"]["fallback"] = int((fb != 0).sum())
     cpu = dict(value=n_sample / dt, unit="galaxies/s", cores=ncores, kind="oracle",
@@ -718,6 +719,8 @@ def main():
     ap.add_argument("--train-n", type=int, default=1 << 20, help="training galaxies (learned workload)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--train-batch", type=int, default=4096)
+    ap.add_argument("--lambda0", type=float, default=1e-3,
+                    help="initial LM damping of the GPU fits (plain and learned; the oracle keeps 1e-3)")
     ap.add_argument("--proposal-max-iter", type=int, default=20,
                     help="LM trials from the learned start before the moment-start fallback")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -804,14 +807,14 @@ def main():
         guess, _ = G.gm_default_guess(gm, db, ctx=ctx)
         if ev:
             ev[1].record(stream)
-        G.gm_fit_batch(gm, db, guess, ctx=ctx, out=(params, chi2, niter, status), err_out=err)
+        G.gm_fit_batch(gm, db, guess, ctx=ctx, out=(params, chi2, niter, status), err_out=err, lambda0=args.lambda0)
         if ev:
             ev[2].record(stream)
             ev[3].record(stream)
 
     def learned_step(ev):
         G.gm_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter, ctx=ctx,
-                         out=(params, chi2, niter, status, fallback), events=ev, err_out=err)
+                         out=(params, chi2, niter, status, fallback), events=ev, err_out=err, lambda0=args.lambda0)
 
     names = ("learned", "plain") if learned else ("plain",)
     plans = {}
@@ -820,9 +823,10 @@ def main():
         for name in names:
             if name == "learned":
                 plans[name] = G.gm_plan_fit_learned(gm, db, mlp, proposal_max_iter=args.proposal_max_iter,
-                                                    errors=True, timing=True, ctx=ctx)
+                                                    errors=True, timing=True, ctx=ctx, lambda0=args.lambda0)
             else:
-                plans[name] = G.gm_plan_fit(gm, db, start=None, errors=True, timing=True, ctx=ctx)
+                plans[name] = G.gm_plan_fit(gm, db, start=None, errors=True, timing=True, ctx=ctx,
+                                            lambda0=args.lambda0)
         log(f"captured {len(plans)} plan(s) in {time.perf_counter() - t0:.2f} s")
 
     results = {}
@@ -871,7 +875,7 @@ def main():
     if args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} galaxies")
         cpu, parity = cpu_baseline(wl["cfg"], args.cpu_sample, seed, gm, mlp, args.proposal_max_iter,
-                                   box=wl.get("box", False), shape=wl.get("shape"))
+                                   box=wl.get("box", False), shape=wl.get("shape"), lam=args.lambda0)
 
     key = f"{args.workload}:{n}:{seed}:{source_hash()}"
     # The metric counts galaxies fitted to within the parity bar of the oracle: the raw
@@ -904,6 +908,7 @@ def main():
                    "launch": "eager calls" if args.eager else "HIP graph replay of captured plans",
                    "init": "learned proposal + moment fallback" if learned else "moment-based",
                    "max_iter": 100, "step_tol": 1e-4,
+                   "lambda0": args.lambda0,
                    **({"proposal_max_iter": args.proposal_max_iter} if learned else {})},
         "roofline": {"bound": "alu", "achieved": head["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": head["achieved"] / PEAK_FP32_TFLOPS, "traffic": TRAFFIC.get(key),

@@ -1815,10 +1815,14 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
 {
     const int tid = threadIdx.x;
     const int H = me.h, W = me.w;
-    const int64_t npix = (int64_t)H * W;
+    // row of pixel q by a float product: cutouts are at most 1024 x 1024, so (q + 0.5) / W is
+    // below 1024 and at least 1 / (2 W) >= 2^-11 away from an integer, while the float
+    // rounding of the product moves it by less than 2^-13
+    const int npix = H * W;
+    const float rW = 1.0f / (float)W;
     double ss = 0.0, sc = 0.0;
-    for (int64_t q = tid; q < npix; q += NT) {
-        int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+    for (int q = tid; q < npix; q += NT) {
+        const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
         if (!(i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) continue;
         float d;
         if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
@@ -1830,8 +1834,8 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
     Moments mo;
     mo.sky0 = sc > 0.0 ? ss / sc : 0.0;
     double f0 = 0.0, fx = 0.0, fy = 0.0, cnt = 0.0, pk = 0.0;
-    for (int64_t q = tid; q < npix; q += NT) {
-        int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+    for (int q = tid; q < npix; q += NT) {
+        const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
         float d;
         if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
         double dp = (double)d - mo.sky0;
@@ -1862,8 +1866,8 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
     if (have) {
         mo.xc = fx / f0;
         mo.yc = fy / f0;
-        for (int64_t q = tid; q < npix; q += NT) {
-            int i = (int)(q / W), j = (int)(q - (int64_t)i * W);
+        for (int q = tid; q < npix; q += NT) {
+            const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
             float d;
             if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
             double dp = (double)d - mo.sky0;

@@ -1894,6 +1894,20 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
 }
 
 // Start vector per family (F::default_guess) from the image moments.
+// The default start of one galaxy from its image moments, written into its
+// parameter row through the model's column map.
+template <class F>
+__device__ inline void moments_guess(const ModelArgs &ma, const Moments &mo, double *out)
+{
+    double pa0 = mo.th0 * 180.0 / kPi;
+    if (pa0 < 0.0) pa0 += 180.0;
+    double nat[F::P];
+    const double ms = mo.mg + 2.5 * log10((double)(ma.nflux > 1 ? ma.nflux : 1));
+    F::default_guess(mo.xc, mo.yc, ms, mo.r0, mo.q0, pa0, mo.sky0, mo.pk, nat);
+    for (int k = 0; k < F::P; ++k)
+        if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
+}
+
 template <class F>
 __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, GuessArgs ga)
 {
@@ -1903,22 +1917,31 @@ __global__ __launch_bounds__(NT) void guess_kernel(ModelArgs ma, BatchArgs ba, G
         const Meta me = ba.meta[g];
         const Moments mo = image_moments(ba, me, ma.m0, sred);
         if (tid == 0) {
-            double pa0 = mo.th0 * 180.0 / kPi;
-            if (pa0 < 0.0) pa0 += 180.0;
             if (ga.moments) {
                 double *m6 = ga.moments + (int64_t)g * 6;
                 m6[0] = mo.xc - 0.5 * me.w; m6[1] = mo.yc - 0.5 * me.h; m6[2] = mo.mg;
                 m6[3] = log(mo.r0); m6[4] = mo.q0; m6[5] = mo.th0;
             }
-            double nat[F::P];
-            const double ms = mo.mg + 2.5 * log10((double)(ma.nflux > 1 ? ma.nflux : 1));
-            F::default_guess(mo.xc, mo.yc, ms, mo.r0, mo.q0, pa0, mo.sky0, mo.pk, nat);
-            double *out = ga.params + (int64_t)g * ma.p;
-            for (int k = 0; k < F::P; ++k)
-                if (ma.col[k] >= 0) out[ma.col[k]] = nat[k];
+            moments_guess<F>(ma, mo, ga.params + (int64_t)g * ma.p);
         }
         __syncthreads();
     }
+}
+
+// The same start from moments a feature pass has already stored: mom8[g] =
+// {sky0, F0, xc, yc, m_g, r0, q0, theta0} and the peak pk[g]; one thread per
+// galaxy.
+template <class F>
+__global__ void guess_stored_kernel(ModelArgs ma, int n_gal, const double *mom8, const double *pk, double *params)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_gal) return;
+    const double *o = mom8 + (int64_t)g * 8;
+    Moments mo;
+    mo.sky0 = o[0]; mo.f0 = o[1]; mo.xc = o[2]; mo.yc = o[3];
+    mo.mg = o[4]; mo.r0 = o[5]; mo.q0 = o[6]; mo.th0 = o[7];
+    mo.pk = pk[g];
+    moments_guess<F>(ma, mo, params + (int64_t)g * ma.p);
 }
 
 static __global__ void fill_int_kernel(int *p, int v) { *p = v; }

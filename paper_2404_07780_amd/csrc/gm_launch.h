@@ -441,6 +441,18 @@ int run_guess(gm_ctx *c, const CallInfo &ci, double *params, double *moments, hi
     return hip_rc(hipGetLastError());
 }
 
+// Default starts from moments already stored by the feature pass (mom8, pk:
+// device arrays of n_gal x 8 and n_gal doubles).
+template <class F>
+int run_guess_stored(gm_ctx *, const CallInfo &ci, const double *mom8, const double *pk, double *params,
+                     hipStream_t st)
+{
+    const int n = ci.b->n_gal;
+    if (n <= 0) return GM_OK;
+    hipLaunchKernelGGL(guess_stored_kernel<F>, dim3((n + 255) / 256), dim3(256), 0, st, ci.ma, n, mom8, pk, params);
+    return hip_rc(hipGetLastError());
+}
+
 template <class F, int NG>
 size_t variant_lds(int K)
 {
@@ -456,6 +468,7 @@ struct Variant {
     int (*errors)(gm_ctx *, const CallInfo &, const double *, double *, double *, hipStream_t) = nullptr;
     int (*image)(gm_ctx *, const CallInfo &, const double *, float *, int, hipStream_t) = nullptr;
     int (*guess)(gm_ctx *, const CallInfo &, double *, double *, hipStream_t) = nullptr;
+    int (*guess_stored)(gm_ctx *, const CallInfo &, const double *, const double *, double *, hipStream_t) = nullptr;
     int (*vjp)(gm_ctx *, const CallInfo &, const double *, const float *, double *, hipStream_t) = nullptr;
     int (*adam)(gm_ctx *, const CallInfo &, const gm_adam_opts *, double *, double *, int32_t *,
                 hipStream_t) = nullptr;
@@ -471,6 +484,7 @@ Variant make_variant()
     v.errors = run_errors<F, NG, KTS...>;
     v.image = run_image<F, NG, KTS...>;
     v.guess = run_guess<F>;
+    v.guess_stored = run_guess_stored<F>;
     v.vjp = run_vjp<F, NG, KTS...>;
     v.adam = run_adam<F, NG, KTS...>;
     return v;

@@ -355,9 +355,9 @@ __global__ void sync_bf16_kernel(int64_t count, const float *p, uint16_t *pb)
 }
 
 // ------------------------------------------------------- features -------
-// mom8[g] = {sky0, F0, xc, yc, m_g, r0, q0, theta0}
+// mom8[g] = {sky0, F0, xc, yc, m_g, r0, q0, theta0}, pk[g] = the peak (both nullable)
 __global__ __launch_bounds__(NT) void features_kernel(BatchArgs ba, double m0, int n_gal, uint16_t *x, int64_t ldx,
-                                                      double *mom8)
+                                                      double *mom8, double *pk)
 {
     __shared__ double sred[NWAVE];
     for (int g = blockIdx.x; g < n_gal; g += gridDim.x) {
@@ -410,6 +410,7 @@ __global__ __launch_bounds__(NT) void features_kernel(BatchArgs ba, double m0, i
             o[0] = mo.sky0; o[1] = mo.f0; o[2] = mo.xc; o[3] = mo.yc;
             o[4] = mo.mg; o[5] = mo.r0; o[6] = mo.q0; o[7] = mo.th0;
         }
+        if (t == 0 && pk) pk[g] = mo.pk;
         __syncthreads();
     }
 }
@@ -810,7 +811,8 @@ int check_proposal_mlp(const gm_mlp *m)
 // meta for a batch (host sizes -> device), through the shared staging path
 int stage_meta(gm_ctx *c, const Match &mt, hipStream_t st, Staged *sg) { return stage(c, mt.ci, nullptr, 0, st, sg); }
 
-int features_launch(gm_ctx *c, const Match &mt, uint16_t *x, int64_t ldx, double *mom8, hipStream_t st)
+int features_launch(gm_ctx *c, const Match &mt, uint16_t *x, int64_t ldx, double *mom8, double *pk,
+                    hipStream_t st)
 {
     Staged sg;
     int rc = stage_meta(c, mt, st, &sg);
@@ -818,7 +820,7 @@ int features_launch(gm_ctx *c, const Match &mt, uint16_t *x, int64_t ldx, double
     const gm_batch *b = mt.ci.b;
     BatchArgs ba{sg.meta, b->data, b->sigma, nullptr, b->omega};
     const int grid = std::min(b->n_gal, std::max(c->num_cu, 1) * 8);
-    hipLaunchKernelGGL(features_kernel, dim3(grid), dim3(NT), 0, st, ba, mt.ci.ma.m0, b->n_gal, x, ldx, mom8);
+    hipLaunchKernelGGL(features_kernel, dim3(grid), dim3(NT), 0, st, ba, mt.ci.ma.m0, b->n_gal, x, ldx, mom8, pk);
     return hipGetLastError() == hipSuccess ? GM_OK : GM_EHIP;
 }
 
@@ -854,15 +856,17 @@ size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t learned_ws_bytes(const gm_mlp *mlp, int n, int p)
 {
     return al256((size_t)n * kInDim * 2) + al256((size_t)n * 8 * 8) + al256((size_t)n * mlp->out_dim * 4) +
-           2 * al256((size_t)n * mlp->hidden * 2) + al256((size_t)n * p * 8) + al256((size_t)n * 4) + 256;
+           2 * al256((size_t)n * mlp->hidden * 2) + al256((size_t)n * p * 8) + al256((size_t)n * 4) +
+           al256((size_t)n * 8) + 256;
 }
 
 // The learned-start fit on the context's MLP workspace (already sized by
-// learned_ws_bytes): moment guess, features, network, decoding, then one LM
-// launch from the valid proposals in which every galaxy whose proposal is
-// invalid or whose fit from it does not converge within the trial budget is
-// refitted from the moment guess by the same workgroup.  events (nullable):
-// before the moment guess, before and after the LM launch, at the end.
+// learned_ws_bytes): features and image moments, the moment guess from them,
+// network, decoding, then one LM launch from the valid proposals in which
+// every galaxy whose proposal is invalid or whose fit from it does not
+// converge within the trial budget is refitted from the moment guess by the
+// same workgroup.  events (nullable): before the features, before and after
+// the LM launch, at the end.
 int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *mlp, const gm_fit_opts *opts,
                 double *params_out, double *chi2_out, int32_t *niter_out, int32_t *status_out, int32_t *fallback_out,
                 void *const *events, hipStream_t st)
@@ -876,12 +880,13 @@ int learned_seq(gm_ctx *ctx, const Match &mt, const Variant *var, const gm_mlp *
     uint16_t *act1 = cv.take<uint16_t>((size_t)n * mlp->hidden);
     double *pdef = cv.take<double>((size_t)n * p);
     int *valid = cv.take<int>(n);
+    double *pk = cv.take<double>(n);
     int rc = mark_event(ctx, events, 0, st);
     if (rc) return rc;
-    // default guess (the refit start), features, proposal
-    rc = var->guess(ctx, mt.ci, pdef, nullptr, st);
+    // features, the default guess (the refit start) from the same moments, proposal
+    rc = features_launch(ctx, mt, x, kInDim, mom8, pk, st);
     if (rc) return rc;
-    rc = features_launch(ctx, mt, x, kInDim, mom8, st);
+    rc = var->guess_stored(ctx, mt.ci, mom8, pk, pdef, st);
     if (rc) return rc;
     uint16_t *Y[17];
     for (int l = 0; l < mlp->n_hidden; ++l) Y[l] = (l & 1) ? act1 : act0;
@@ -1032,7 +1037,7 @@ int gm_features(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, uint1
     if (batch->n_gal == 0) return GM_OK;
     if (!x_out || ldx < kInDim || ldx % 8 || !aligned16(x_out)) return GM_EINVAL;
     Scoped sd(ctx->device);
-    return features_launch(ctx, mt, x_out, ldx, moments_out, (hipStream_t)stream);
+    return features_launch(ctx, mt, x_out, ldx, moments_out, nullptr, (hipStream_t)stream);
 }
 
 int gm_proposal_targets(gm_ctx *ctx, const gm_model *model, const gm_batch *batch, const double *truth,

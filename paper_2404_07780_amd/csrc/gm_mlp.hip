@@ -88,28 +88,35 @@ struct GemmArgs {
 };
 
 // Staging of one 64 x 32 (rows x K) operand slice into an LDS tile
-// T[r][k] (pitch LDK), zero outside R x K, in two halves so that the global
+// T[r][k] (pitch LDK), zero outside R x K, in three steps so that the global
 // reads of the next slice can be issued before the matrix-core work on the
-// current one: fetch (global -> registers), then put (registers -> LDS).
+// current one: gather_piece (the row indices of an optional row map),
+// read_piece (global -> registers), put (registers -> LDS).  A workgroup
+// gathers for both operands before it reads either: the memory counter the
+// reads wait on counts in order, so a gather issued after a data read would
+// make that read a wait of its own.  Both are called with k0 < K (K: the end
+// of the workgroup's K range) and R >= 1.
 //
 // K-contiguous operand X(r, k) = P[map(r) * ld + k]: each thread reads eight
 // consecutive K values of one row (16 bytes) and stores them with one
 // 16-byte LDS write.
 struct KMajorPiece {
     u32x4 v;
+    int64_t row;
 };
 
-__device__ inline void fetch_kmajor(KMajorPiece &f, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
-                                    int k0, int K)
+__device__ inline void gather_kmajor(KMajorPiece &f, const int *map, int r0, int R, int, int)
+{
+    const int rr = r0 + (threadIdx.x >> 2);
+    f.row = map ? (int64_t)map[min(rr, R - 1)] : (int64_t)rr;
+}
+
+__device__ inline void read_kmajor(KMajorPiece &f, const uint16_t *P, int64_t ld, int r0, int R, int k0, int K)
 {
     const int t = threadIdx.x;
-    const int r = t >> 2, kc = (t & 3) * 8;
+    const int rr = r0 + (t >> 2), k = k0 + (t & 3) * 8;
     f.v = u32x4{0u, 0u, 0u, 0u};
-    const int rr = r0 + r, k = k0 + kc;
-    if (rr < R && k < K) {
-        const int64_t row = map ? (int64_t)map[rr] : (int64_t)rr;
-        f.v = *reinterpret_cast<const u32x4 *>(P + row * ld + k);
-    }
+    if (rr < R && k < K) f.v = *reinterpret_cast<const u32x4 *>(P + f.row * ld + k);
 }
 
 __device__ inline void put_kmajor(uint16_t *T, const KMajorPiece &f)
@@ -124,22 +131,30 @@ __device__ inline void put_kmajor(uint16_t *T, const KMajorPiece &f)
 // multiple of 8, so a pair is either inside R or outside it).
 struct RMajorPiece {
     uint32_t v[4];
+    int64_t row[4];
 };
 
-__device__ inline void fetch_rmajor(RMajorPiece &f, const uint16_t *P, int64_t ld, const int *map, int r0, int R,
-                                    int k0, int K)
+__device__ inline void gather_rmajor(RMajorPiece &f, const int *map, int, int, int k0, int K)
+{
+    const int kq = 4 * (threadIdx.x >> 5);
+    // one branch on the map for the four indices, each clamped to K - 1
+    // rather than guarded (a guarded read ends in a wait)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) f.row[e] = k0 + kq + e;
+    if (map) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f.row[e] = map[min(k0 + kq + e, K - 1)];
+    }
+}
+
+__device__ inline void read_rmajor(RMajorPiece &f, const uint16_t *P, int64_t ld, int r0, int R, int k0, int K)
 {
     const int t = threadIdx.x;
-    const int rp = 2 * (t & 31), kq = 4 * (t >> 5);
-    const int rr = r0 + rp;
+    const int rr = r0 + 2 * (t & 31), kq = 4 * (t >> 5);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int k = k0 + kq + e;
         f.v[e] = 0u;
-        if (k < K && rr < R) {
-            const int64_t row = map ? (int64_t)map[k] : (int64_t)k;
-            f.v[e] = *reinterpret_cast<const uint32_t *>(P + row * ld + rr);
-        }
+        if (k0 + kq + e < K && rr < R) f.v[e] = *reinterpret_cast<const uint32_t *>(P + f.row[e] * ld + rr);
     }
 }
 
@@ -164,13 +179,22 @@ struct PieceOf<true> {
 };
 
 template <bool RMAJOR>
-__device__ inline void fetch(typename PieceOf<RMAJOR>::type &f, const uint16_t *P, int64_t ld, const int *map, int r0,
-                             int R, int k0, int K)
+__device__ inline void gather_piece(typename PieceOf<RMAJOR>::type &f, const int *map, int r0, int R, int k0, int K)
 {
     if constexpr (RMAJOR)
-        fetch_rmajor(f, P, ld, map, r0, R, k0, K);
+        gather_rmajor(f, map, r0, R, k0, K);
     else
-        fetch_kmajor(f, P, ld, map, r0, R, k0, K);
+        gather_kmajor(f, map, r0, R, k0, K);
+}
+
+template <bool RMAJOR>
+__device__ inline void read_piece(typename PieceOf<RMAJOR>::type &f, const uint16_t *P, int64_t ld, int r0, int R,
+                                  int k0, int K)
+{
+    if constexpr (RMAJOR)
+        read_rmajor(f, P, ld, r0, R, k0, K);
+    else
+        read_kmajor(f, P, ld, r0, R, k0, K);
 }
 
 template <bool RMAJOR>
@@ -204,17 +228,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     typename PieceOf<AT>::type fa;
     typename PieceOf<!BT>::type fb;
+    const int *bmap = BT ? nullptr : g.bmap;
     if (kbeg < kend) {
-        fetch<AT>(fa, g.a, g.lda, g.amap, m0, g.M, kbeg, kend);
-        fetch<!BT>(fb, g.b, g.ldb, BT ? nullptr : g.bmap, n0, g.N, kbeg, kend);
+        gather_piece<AT>(fa, g.amap, m0, g.M, kbeg, kend);
+        gather_piece<!BT>(fb, bmap, n0, g.N, kbeg, kend);
+        read_piece<AT>(fa, g.a, g.lda, m0, g.M, kbeg, kend);
+        read_piece<!BT>(fb, g.b, g.ldb, n0, g.N, kbeg, kend);
     }
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
         put<AT>(As, fa);
         put<!BT>(Bs, fb);
         __syncthreads();
         if (k0 + GK < kend) {       // the next slice's global reads overlap this slice's products
-            fetch<AT>(fa, g.a, g.lda, g.amap, m0, g.M, k0 + GK, kend);
-            fetch<!BT>(fb, g.b, g.ldb, BT ? nullptr : g.bmap, n0, g.N, k0 + GK, kend);
+            gather_piece<AT>(fa, g.amap, m0, g.M, k0 + GK, kend);
+            gather_piece<!BT>(fb, bmap, n0, g.N, k0 + GK, kend);
+            read_piece<AT>(fa, g.a, g.lda, m0, g.M, k0 + GK, kend);
+            read_piece<!BT>(fb, g.b, g.ldb, n0, g.N, k0 + GK, kend);
         }
         bf16x8 af[2], bfr[2];
 #pragma unroll

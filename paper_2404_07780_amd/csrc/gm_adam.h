@@ -54,12 +54,14 @@ __device__ void evaluate_grad(const double *u, const ModelArgs &ma, const BatchA
             __syncthreads();
             const int i = ti0 + r;
             if (i >= H) continue;
+            float dv[4], wv[4];
+            strip_weights(ba, me.img_off + (int64_t)i * W, tj0 + 4 * cg, W, dv, wv);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int j = tj0 + 4 * cg + t;
                 if (j >= W) continue;
-                float d;
-                const float wgt = pixel_weight(ba, me.img_off + (int64_t)i * W + j, d);
+                const float d = dv[t];
+                const float wgt = wv[t];
                 float R = 0.0f;
                 if (wgt != 0.0f) {
                     const double pdx = ((double)j + 0.5) - 0.5 * W, pdy = 0.5 * H - ((double)i + 0.5);

@@ -656,6 +656,31 @@ __device__ inline float pixel_weight(const BatchArgs &ba, int64_t idx, float &d)
     return ok ? 1.0f / (s * s) : 0.0f;
 }
 
+// pixel_weight of the four pixels j0 .. j0 + 3 of the row starting at rowoff,
+// read together (columns past W - 1 read pixel W - 1; the caller skips them):
+// one wait for the strip instead of one per pixel.
+__device__ inline void strip_weights(const BatchArgs &ba, int64_t rowoff, int j0, int W, float (&d)[4],
+                                     float (&w)[4])
+{
+    float s[4];
+    int m[4] = {1, 1, 1, 1};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t idx = rowoff + min(j0 + t, W - 1);
+        d[t] = ba.data[idx];
+        s[t] = ba.sigma[idx];
+    }
+    if (ba.omega) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m[t] = ba.omega[rowoff + min(j0 + t, W - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool ok = m[t] != 0 && s[t] > 0.0f && isfinite(s[t]) && isfinite(d[t]);
+        w[t] = ok ? 1.0f / (s[t] * s[t]) : 0.0f;
+    }
+}
+
 // A bootstrap replica (r >= 0) of galaxy g: every pixel weight is multiplied
 // by a Poisson(1) deviate drawn from Philox4x32-10 keyed by (k0, k1), counter
 // {pixel / 4, g, r, 1}, word pixel mod 4 (pixel: row-major index in the
@@ -734,13 +759,14 @@ __device__ void evaluate(const double *u, const ModelArgs &ma, const BatchArgs &
             if (i < H) {
                 float bw[4] = {1.0f, 1.0f, 1.0f, 1.0f};
                 if (bt.r >= 0) boot_weights(bt, (int64_t)i * W + tj0 + 4 * cg, bw);
+                float dv[4], wv[4];
+                strip_weights(ba, me.img_off + (int64_t)i * W, tj0 + 4 * cg, W, dv, wv);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int j = tj0 + 4 * cg + t;
                     if (j >= W) continue;
-                    const int64_t idx = me.img_off + (int64_t)i * W + j;
-                    float d;
-                    const float wgt = pixel_weight(ba, idx, d) * bw[t];
+                    const float d = dv[t];
+                    const float wgt = wv[t] * bw[t];
                     if (wgt == 0.0f) continue;
                     const double pdx = ((double)j + 0.5) - 0.5 * W, pdy = 0.5 * H - ((double)i + 0.5);
                     const double res = (double)d - (acc0[t] + F::sky_at(sh.prep, pdx, pdy));

@@ -1919,7 +1919,6 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
     return mo;
 }
 
-// Start vector per family (F::default_guess) from the image moments.
 // The default start of one galaxy from its image moments, written into its
 // parameter row through the model's column map.
 template <class F>

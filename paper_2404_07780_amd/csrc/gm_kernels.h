@@ -1837,6 +1837,35 @@ struct Moments {
     double sky0, f0, xc, yc, r0, q0, th0, mg, pk;
 };
 
+// Pixels per thread that a moments pass reads at once.
+constexpr int kMomU = 4;
+
+// This thread's pixels q0 + u NT (u < kMomU) of a cutout of npix pixels at
+// off: data d, sigma s and ok = (pixel_weight != 0) (false past the cutout,
+// whose reads take its last pixel), all reads issued before any value is
+// used, the mask's in one uniform branch: one wait per batch.
+__device__ inline void moment_pixels(const BatchArgs &ba, int64_t off, int q0, int npix, float (&d)[kMomU],
+                                     float (&s)[kMomU], bool (&ok)[kMomU])
+{
+    int m[kMomU];
+#pragma unroll
+    for (int u = 0; u < kMomU; ++u) {
+        const int64_t idx = off + min(q0 + u * NT, npix - 1);
+        d[u] = ba.data[idx];
+        s[u] = ba.sigma[idx];
+        m[u] = 1;
+    }
+    if (ba.omega) {
+#pragma unroll
+        for (int u = 0; u < kMomU; ++u) m[u] = ba.omega[off + min(q0 + u * NT, npix - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kMomU; ++u) {
+        const bool use = m[u] != 0 && s[u] > 0.0f && isfinite(s[u]) && isfinite(d[u]);
+        ok[u] = q0 + u * NT < npix && (use ? 1.0f / (s[u] * s[u]) : 0.0f) != 0.0f;
+    }
+}
+
 __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, double m0, double *sred)
 {
     const int tid = threadIdx.x;
@@ -1846,29 +1875,41 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
     // rounding of the product moves it by less than 2^-13
     const int npix = H * W;
     const float rW = 1.0f / (float)W;
+    // each thread takes its pixels q = tid + k NT in increasing k, kMomU at a time
     double ss = 0.0, sc = 0.0;
-    for (int q = tid; q < npix; q += NT) {
-        const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
-        if (!(i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) continue;
-        float d;
-        if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-        ss += d;
-        sc += 1.0;
+    for (int q0 = tid; q0 < npix; q0 += kMomU * NT) {
+        float d[kMomU], sg[kMomU];
+        bool ok[kMomU];
+        moment_pixels(ba, me.img_off, q0, npix, d, sg, ok);
+#pragma unroll
+        for (int u = 0; u < kMomU; ++u) {
+            const int q = q0 + u * NT;
+            const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
+            if (ok[u] && (i < 2 || i >= H - 2 || j < 2 || j >= W - 2)) {
+                ss += d[u];
+                sc += 1.0;
+            }
+        }
     }
     ss = block_sum(ss, sred);
     sc = block_sum(sc, sred);
     Moments mo;
     mo.sky0 = sc > 0.0 ? ss / sc : 0.0;
     double f0 = 0.0, fx = 0.0, fy = 0.0, cnt = 0.0, pk = 0.0;
-    for (int q = tid; q < npix; q += NT) {
-        const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
-        float d;
-        if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-        double dp = (double)d - mo.sky0;
-        if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
-        double x = j + 0.5, y = (double)H - i - 0.5;
-        f0 += dp; fx += dp * x; fy += dp * y; cnt += 1.0;
-        pk = fmax(pk, dp);
+    for (int q0 = tid; q0 < npix; q0 += kMomU * NT) {
+        float d[kMomU], sg[kMomU];
+        bool ok[kMomU];
+        moment_pixels(ba, me.img_off, q0, npix, d, sg, ok);
+#pragma unroll
+        for (int u = 0; u < kMomU; ++u) {
+            const double dp = (double)d[u] - mo.sky0;
+            if (!ok[u] || !(dp > 3.0 * (double)sg[u])) continue;
+            const int q = q0 + u * NT;
+            const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
+            double x = j + 0.5, y = (double)H - i - 0.5;
+            f0 += dp; fx += dp * x; fy += dp * y; cnt += 1.0;
+            pk = fmax(pk, dp);
+        }
     }
     f0 = block_sum(f0, sred);
     fx = block_sum(fx, sred);
@@ -1892,14 +1933,19 @@ __device__ inline Moments image_moments(const BatchArgs &ba, const Meta &me, dou
     if (have) {
         mo.xc = fx / f0;
         mo.yc = fy / f0;
-        for (int q = tid; q < npix; q += NT) {
-            const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
-            float d;
-            if (pixel_weight(ba, me.img_off + q, d) == 0.0f) continue;
-            double dp = (double)d - mo.sky0;
-            if (!(dp > 3.0 * (double)ba.sigma[me.img_off + q])) continue;
-            double dx = j + 0.5 - mo.xc, dy = (double)H - i - 0.5 - mo.yc;
-            mxx += dp * dx * dx; myy += dp * dy * dy; mxy += dp * dx * dy;
+        for (int q0 = tid; q0 < npix; q0 += kMomU * NT) {
+            float d[kMomU], sg[kMomU];
+            bool ok[kMomU];
+            moment_pixels(ba, me.img_off, q0, npix, d, sg, ok);
+#pragma unroll
+            for (int u = 0; u < kMomU; ++u) {
+                const double dp = (double)d[u] - mo.sky0;
+                if (!ok[u] || !(dp > 3.0 * (double)sg[u])) continue;
+                const int q = q0 + u * NT;
+                const int i = (int)(((float)q + 0.5f) * rW), j = q - i * W;
+                double dx = j + 0.5 - mo.xc, dy = (double)H - i - 0.5 - mo.yc;
+                mxx += dp * dx * dx; myy += dp * dy * dy; mxy += dp * dx * dy;
+            }
         }
     }
     mxx = block_sum(mxx, sred);

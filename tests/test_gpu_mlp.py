@@ -173,6 +173,28 @@ def test_features_masked():
     _features_case(b, omega=b.omega)
 
 
+@pytest.mark.parametrize("case", ["sersic64", "uneven", "masked"])
+def test_feature_moments_equal_default_guess_moments(case):
+    # the learned fit builds its refit start from the moments the feature pass
+    # stores, the plain fit's start recomputes them: the same bits either way
+    if case == "masked":
+        b = oracle_mixed(40, seed=3)["sersic"]
+        omega = b.omega
+    else:
+        b, omega = oracle_batch(case, 12, seed=1), None
+    gm = G.Model.from_spec(S.MODEL_SPECS[b.model])
+    db = _dev(b, omega=omega)
+    m8 = G.gm_features(gm, db)[1].cpu().numpy()        # sky0 F0 xc yc m_g r0 q0 theta0
+    m6 = G.gm_default_guess(gm, db)[1].cpu().numpy()   # xc - W/2, yc - H/2, m_g, ln r0, q0, theta0
+    w, h = np.asarray(b.w, np.float64), np.asarray(b.h, np.float64)
+    assert np.array_equal(m6[:, 0], m8[:, 2] - 0.5 * w)
+    assert np.array_equal(m6[:, 1], m8[:, 3] - 0.5 * h)
+    assert np.array_equal(m6[:, 2], m8[:, 4])
+    assert np.allclose(m6[:, 3], np.log(m8[:, 5]), rtol=1e-15, atol=1e-15)
+    assert np.array_equal(m6[:, 4], m8[:, 6])
+    assert np.array_equal(m6[:, 5], m8[:, 7])
+
+
 def test_targets_and_decode_match_oracle():
     b = oracle_batch("sersic64", 32, seed=5)
     gm = G.Model.from_spec(S.MODEL_SPECS["sersic"])
